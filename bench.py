@@ -1,0 +1,195 @@
+#!/usr/bin/env python3
+"""Benchmark of the stiff-chemistry hot path on one MI355X.
+
+Workload (default): the bulk-sparse detonation patch, 256 x 256 x 32 =
+2,097,152 cells of the 9-species / 21-reaction synthetic H2-air mechanism,
+dt = 5e-9 s, rtol 1e-8 / atol 1e-14, FP64.  One step = one chem_integrate
+call over the whole patch (screen, bulk rounds, compaction, sparse phase),
+restarted from a pristine device copy of the initial state (the copy is
+inside the timed region).  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+R_GAS = 8.314462618
+FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector (256 CU x 2.4 GHz x 128 FLOP/clk)
+HBM_PEAK_GBS = 8000.0
+METRIC = "chemistry cell-steps/s, plain FP64 vs batched/mixed/surrogate at fixed error"
+
+
+def mech_flop_model(path):
+    """Algorithmic FLOPs per RHS / Jacobian / LU / solve, counted from the
+    mechanism's nonzeros (exp, log and divide count as one FLOP)."""
+    sys.path.insert(0, os.path.join(ROOT, "paper_2510_23993_amd", "csrc"))
+    import gen_mech
+    names, rx = gen_mech.parse_structure(path)
+    ns, nr = len(names), len(rx)
+    n = ns + 1
+    nnz_f = sum(len(r["re"]) for r in rx)
+    nnz_r = sum(len(r["pr"]) for r in rx)
+    nnz = nnz_f + nnz_r
+    n_tb = sum(1 for r in rx if r["type"] in (1, 2))
+    n_fo = sum(1 for r in rx if r["type"] == 2)
+    f_thermo = 20 * ns                      # NASA-7 h and s (Horner) per species
+    f_conc = 3 * ns                         # C, floor, ln C
+    f_arr = 5 * nr                          # ln kf contraction with (1, ln T, -1/T)
+    f_kc = 2 * nnz + 2 * nr                 # ln Kc row of nu against g/RT, + dnu ln(Pref/RT)
+    f_lnq = 2 * nnz + 2 * nr                # nu' and nu'' contractions against ln C, exp
+    f_tb = 2 * ns * n_tb + n_tb             # [M] sums and multiply
+    f_fo = 30 * n_fo                        # falloff: Pr, Fcent, Troe broadening
+    f_om = 2 * nnz + nr                     # production omega = nu (qf - qr)
+    f_out = 6 * ns + 4                      # dY/dt, c_v, energy sum, dT/dt
+    F_rhs = f_thermo + f_conc + f_arr + f_kc + f_lnq + f_tb + f_fo + f_om + f_out
+    dep = [len(r["re"]) + len(r["pr"]) if r["type"] == 0 else ns for r in rx]
+    F_jac = F_rhs + sum(2 * (len(r["re"]) + len(r["pr"])) * d for r, d in zip(rx, dep)) \
+        + 6 * n * nr + 4 * n * n
+    F_lu = (2 * n ** 3) // 3
+    F_solve = 2 * n * n
+    return {"F_rhs": F_rhs, "F_jac": F_jac, "F_lu": F_lu, "F_solve": F_solve, "n": n,
+            "ns": ns, "nr": nr}
+
+
+def algorithmic_flops(model, st):
+    return (st["rhs_evals"] * model["F_rhs"] + st["jac_evals"] * model["F_jac"]
+            + st["lu_facts"] * model["F_lu"] + st["lin_solves"] * model["F_solve"])
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--nz", type=int, default=32)
+    ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--atol", type=float, default=1e-14)
+    ap.add_argument("--algorithm", type=int, default=1)
+    ap.add_argument("--cpu-sample", type=int, default=4096)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--opt", action="append", default=[], help="key=value library option")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the chemistry step "
+                          "shards by cells with no exchange, see DESIGN.md for the multi-GPU design",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    import paper_2510_23993_amd as chem
+    from synth import fields
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    mech = chem.Mechanism(fields.M9_PATH)
+    ctx = chem.Context(mech, algorithm=args.algorithm)
+    for kv in args.opt:
+        k, v = kv.split("=")
+        ctx.set_option(k, float(v))
+
+    cells = fields.c2_field(256, 256, args.nz)
+    n = cells.T.size
+    T_d = torch.as_tensor(cells.T, device=dev)
+    p_d = torch.as_tensor(cells.p, device=dev)
+    Y0 = torch.as_tensor(cells.Y, device=dev).contiguous()
+    rho = torch.empty(n, dtype=torch.float64, device=dev)
+    e = torch.empty(n, dtype=torch.float64, device=dev)
+    ctx.prepare_state(T_d, p_d, Y0, rho, e)        # reactor inputs built on the device
+    Y = torch.empty_like(Y0)
+    T = torch.empty_like(T_d)
+    status = torch.empty(n, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def step(stats):
+        Y.copy_(Y0)
+        T.copy_(T_d)
+        return ctx.integrate(rho, e, Y, T, cells.dt, args.rtol, args.atol, status=status, stats=stats)
+
+    # warmup (also yields the per-call counters used for the FLOP count)
+    st = None
+    for _ in range(max(1, args.warmup)):
+        st = step(True)
+    torch.cuda.synchronize()
+    # timed region: K steps, no host synchronisation inside
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step(False)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = 1e3 * wall / args.steps
+    ev_ms = ev0.elapsed_time(ev1) / args.steps
+    value = n * args.steps / wall
+
+    # per-call device time of the integration (library events) and FLOPs
+    st = step(True)
+    torch.cuda.synchronize()
+    model = mech_flop_model(fields.M9_PATH)
+    flops = algorithmic_flops(model, st)
+    t_call_s = st["t_total_ms"] * 1e-3
+    achieved = flops / t_call_s / 1e12
+    status_h = status.cpu().numpy()
+    out = {
+        "metric": METRIC, "value": value, "unit": "cell-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"bulk-sparse detonation patch 256x256x{args.nz} ({n} cells), "
+                   "9-species/21-reaction synthetic H2-air mechanism, dt 5e-9 s",
+                   "rtol": args.rtol, "atol": args.atol,
+                   "algorithm": "bulk-sparse" if args.algorithm == 1 else "plain",
+                   "options": {k: ctx.get_option(k) for k in (
+                       "t_react_min", "kmax_bulk", "nactive_star", "kmax_sparse", "max_rounds",
+                       "grid_waves")}},
+        "event_ms_per_step": ev_ms,
+        "stats": {k: st[k] for k in ("n_active0", "n_active_after_bulk", "n_bulk_rounds",
+                                     "steps_total", "attempts_total", "rhs_evals", "jac_evals",
+                                     "lu_facts", "lin_solves", "max_steps_cell", "t_total_ms")},
+        "status_counts": np.bincount(status_h, minlength=8).tolist(),
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "integration pipeline (bulk rounds + sparse phase)",
+                     "flops_per_call": flops, "flop_model": model},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(cells, args, n)
+    print(json.dumps(out))
+
+
+def cpu_baseline(cells, args, n_full):
+    """The oracle (plain C + OpenMP, FP64, no skip) on a stratified sample of
+    the same field at the same tolerances, scaled to the full field."""
+    import oracle
+    from synth import fields
+    orc = oracle.Oracle(fields.M9_PATH)
+    rng = np.random.default_rng(1002)
+    idx = []
+    for c in np.unique(cells.cls):
+        members = np.where(cells.cls == c)[0]
+        k = max(1, int(round(args.cpu_sample * members.size / n_full)))
+        idx.append(rng.choice(members, size=min(k, members.size), replace=False))
+    idx = np.sort(np.concatenate(idx))
+    rho, e = orc.state_from_TPY(cells.T[idx], cells.p[idx], cells.Y[:, idx])
+    threads = len(os.sched_getaffinity(0))
+    t0 = time.perf_counter()
+    orc.integrate(rho, e, cells.Y[:, idx], cells.dt, args.rtol, args.atol, T=cells.T[idx],
+                  nthreads=threads)
+    wall = time.perf_counter() - t0
+    return {"value": idx.size / wall, "unit": "cell-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{idx.size} cells stratified by class (cold/induction/burnt) from the same "
+                      f"field, same rtol/atol, {wall:.2f} s wall"}
+
+
+if __name__ == "__main__":
+    main()

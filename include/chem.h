@@ -1,0 +1,183 @@
+/*
+ * chem.h -- C ABI of the MI355X stiff-chemistry library (libchem.so).
+ *
+ * The operation: every cell is an independent constant-volume ideal-gas
+ * reactor whose density rho and mass-specific internal energy e stay fixed
+ * while its composition Y and temperature T are advanced from t = 0 to
+ * t = dt, the chemistry substep of a Strang-split reacting-flow step
+ * (paper Sec. 2.1, Eq. 5-6: dY_k/dt = W_k Omega_k / rho, and the
+ * temperature equation read as dT/dt = -sum_k u_k Omega_k / (rho c_v) with
+ * the mass-based mixture c_v and molar internal energies u_k).  The initial
+ * temperature is recovered from (e, Y) by Newton iteration at constant rho
+ * and e (Sec. 2.1).  Cells colder than a threshold, or masked as solid,
+ * are not integrated (Alg. 2 and Alg. 3, "T < T_reaction_min or
+ * is_solid").
+ *
+ * Rates use the matrix form: every reaction's forward and reverse rate of
+ * progress is a stoichiometric contraction against log-concentrations
+ * followed by exp (Sec. 2.1, kinetics adapted from a matrix-based solver).
+ * Concentrations are floored at 1e-300 mol/m^3 inside the logarithm.
+ * Integration is implicit (variable-order BDF, modified Newton with an
+ * analytic Jacobian and LU with partial pivoting, FP64).  With the
+ * bulk-sparse algorithm (Alg. 3) every active cell first runs rounds of at
+ * most kmax_bulk steps while more than nactive_star cells remain active;
+ * the remaining stiff cells are then compacted through an index map and
+ * integrated to completion (Sec. 3.2).
+ *
+ * Units: SI (kg, m, s, mol, J, K); e includes formation energy (NASA-7
+ * absolute enthalpy basis).  Mechanism files use CHEMKIN units
+ * (cm, mol, s, cal/mol, g/mol); see the mechanism file format in the
+ * package documentation.
+ *
+ * Memory and streams: every state array passed to the integration calls is
+ * caller-owned DEVICE memory (hipMalloc'd or a torch CUDA tensor) and stays
+ * owned by the caller; the library never frees or reallocates it.  The
+ * library owns its workspace (grown on demand, reused across calls).  All
+ * work is enqueued on the context's stream, in order; calls return as soon
+ * as the work is enqueued unless a chem_stats pointer is passed, in which
+ * case the call synchronises the stream and fills it.
+ *
+ * Errors: 0 = CHEM_OK; negative = hard error (nothing enqueued, message in
+ * chem_last_error(), thread-local); positive CHEM_W_INCOMPLETE = the work
+ * ran but at least one cell did not reach dt (only reported when a
+ * chem_stats pointer forces a synchronisation; per-cell status says which).
+ */
+#ifndef CHEM_H
+#define CHEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    CHEM_OK = 0,
+    CHEM_W_INCOMPLETE = 1,
+    CHEM_E_INVAL = -1,   /* NULL pointer, ncell < 0, dt <= 0, rtol <= 0, ldY < ncell, bad key */
+    CHEM_E_HIP = -2,     /* HIP runtime error */
+    CHEM_E_NOMEM = -3,   /* device allocation failed */
+    CHEM_E_MECH = -4,    /* parse error, unbalanced reaction, or no compiled kernel for it */
+    CHEM_E_STATE = -5    /* object used in a wrong state */
+};
+
+/* per-cell status codes written to the status array */
+enum {
+    CHEM_ST_DONE = 0,        /* reached dt */
+    CHEM_ST_SKIPPED = 1,     /* cold (T < t_react_min) or masked: not integrated, Y unchanged */
+    CHEM_ST_KMAX = 2,        /* step limit reached; Y, T hold the last accepted state */
+    CHEM_ST_FAIL = 3,        /* Newton / step-size failure; last accepted state kept */
+    CHEM_ST_TINV = 4,        /* T inversion failed or rho/e not finite or rho <= 0 */
+    CHEM_ST_SURR_OK = 5,     /* surrogate increment accepted */
+    CHEM_ST_SURR_REJ = 6     /* surrogate rejected, cell integrated implicitly instead */
+};
+
+typedef struct chem_mech_s* chem_mech_t; /* immutable after load; shareable across contexts */
+typedef struct chem_ctx_s* chem_ctx_t;   /* owns workspace + stream binding; not thread-safe */
+
+typedef struct {
+    int64_t ncell;              /* cells handed in */
+    int64_t n_active0;          /* cells integrated (after screening) */
+    int64_t n_active_after_bulk;/* cells still unfinished when the bulk phase stopped */
+    int64_t n_bulk_rounds;      /* bulk rounds that ran */
+    int64_t n_sparse;           /* cells handed to the sparse phase */
+    int64_t n_incomplete;       /* cells that did not reach dt */
+    int64_t n_fallback;         /* surrogate: cells sent back to the implicit path */
+    int64_t steps_total;        /* accepted BDF steps */
+    int64_t attempts_total;     /* attempted steps (accepted + rejected + retried) */
+    int64_t rhs_evals, jac_evals, lu_facts, lin_solves;
+    int64_t max_steps_cell;     /* most attempts spent by one cell */
+    double t_total_ms;          /* device time of the call (events on the context stream) */
+} chem_stats;
+
+/* One AMR box (a separately allocated grid): device pointers, column-major
+ * Y[k * ldY + i], its own dt.  status and mask may be NULL. */
+typedef struct {
+    int64_t ncell;
+    const double* rho;
+    const double* e;
+    double* Y;
+    int64_t ldY;
+    double* T;
+    const uint8_t* mask;
+    uint8_t* status;
+    double dt;
+    int level;
+} chem_box;
+
+/* Parse a mechanism file (host), check element balance, select the kernels
+ * compiled for its reaction structure, and upload its parameters to the
+ * current device.  Errors: CHEM_E_INVAL (NULL), CHEM_E_MECH (parse error,
+ * unbalanced reaction, structure without compiled kernels), CHEM_E_HIP. */
+int chem_load_mechanism(const char* path, chem_mech_t* out);
+/* Species / reaction counts and molecular weights [kg/mol] (host array owned
+ * by the mechanism). */
+int chem_mech_info(chem_mech_t m, int* nspec, int* nreac, const double** W_host);
+int chem_species_name(chem_mech_t m, int k, const char** name);
+void chem_free_mechanism(chem_mech_t m);
+
+/* Create a context on `device` bound to `hip_stream` (a hipStream_t; NULL =
+ * the default stream).  Allocates nothing large until the first call. */
+int chem_ctx_create(chem_mech_t m, int device, void* hip_stream, chem_ctx_t* out);
+void chem_ctx_destroy(chem_ctx_t c);
+
+/* Options (all numeric):
+ *   algorithm     0 = plain (Alg. 2: every unmasked cell, one thread per cell,
+ *                 no temperature skip), 1 = bulk-sparse (Alg. 3), default 1
+ *   t_react_min   K, cells colder than this are skipped (bulk-sparse), default 500
+ *   kmax_bulk     steps per bulk round (Alg. 3 Sec. 2), default 5
+ *   nactive_star  bulk rounds continue while more cells than this are active, default 1e4
+ *   kmax_sparse   step limit of the sparse phase / plain path, default 1e5
+ *   max_rounds    bulk-round launches enqueued per call (device decides how many run), default 24
+ *   grid_waves    waves per CU of the persistent integration kernel, default 0 (auto)
+ *   precision     0 = FP64 rates (default); other values reserved for mixed-precision kernels
+ *   use_graph     1 = capture the enqueued pipeline of chem_integrate_boxes in a
+ *                 hipGraph and replay it while the box table is unchanged, default 1
+ * Returns CHEM_E_INVAL for an unknown key or out-of-range value. */
+int chem_set_option(chem_ctx_t c, const char* key, double value);
+int chem_get_option(chem_ctx_t c, const char* key, double* value);
+
+/* Integrate ncell cells over [0, dt].
+ *   rho, e   [ncell] device, read only
+ *   Y        [nspec][ldY] device, column-major (Y[k*ldY + i]), in/out
+ *   T        [ncell] device, in: temperature guess (values outside
+ *            (100, 6000) K mean none), out: final temperature
+ *   skip_mask[ncell] device or NULL: nonzero = solid cell, not integrated
+ *   status   [ncell] device or NULL: per-cell CHEM_ST_* code
+ *   rtol, atol: BDF tolerances, error weights 1/(rtol |y| + atol) on (Y, T)
+ *   stats    NULL (asynchronous) or a host struct filled after a stream sync
+ * Returns CHEM_OK, CHEM_W_INCOMPLETE (only with stats), or a negative error. */
+int chem_integrate(chem_ctx_t c, int64_t ncell, const double* rho, const double* e, double* Y,
+                   int64_t ldY, double* T, const uint8_t* skip_mask, uint8_t* status, double dt,
+                   double rtol, double atol, chem_stats* stats);
+
+/* Integrate many separately allocated boxes, each over its own dt, in one
+ * enqueued pipeline (one screening pass, one compaction, persistent
+ * integration kernels over all boxes; Sec. 3.2.1 multigrid fusion with an
+ * index map).  The box table is copied; pointers must stay valid until the
+ * work completes.  Same return conventions as chem_integrate. */
+int chem_integrate_boxes(chem_ctx_t c, int nbox, const chem_box* boxes, double rtol, double atol,
+                         chem_stats* stats);
+
+/* (T, p, Y) -> (rho, e) on the device for ncell cells (ideal gas, NASA-7):
+ * a convenience to build reactor inputs from primitive states.  T, p
+ * [ncell], Y [nspec][ldY]; rho, e [ncell] outputs.  Asynchronous. */
+int chem_prepare_state(chem_ctx_t c, int64_t ncell, const double* T, const double* p,
+                       const double* Y, int64_t ldY, double* rho, double* e);
+
+/* Right-hand side and analytic Jacobian of the reactor ODE for ncell states
+ * (device arrays): y [nspec+1][ncell] column-major (Y then T), rho [ncell];
+ * f [nspec+1][ncell]; J [(nspec+1)^2][ncell] with J[(i*(nspec+1)+j)*ncell + c]
+ * = d f_i / d y_j (J may be NULL).  Asynchronous.  For testing the kernels'
+ * building blocks against the oracle. */
+int chem_eval_rhs(chem_ctx_t c, int64_t ncell, const double* rho, const double* y, double* f,
+                  double* J);
+
+int chem_load_surrogate(chem_ctx_t c, const char* weights_path);
+int chem_synchronize(chem_ctx_t c);
+const char* chem_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,215 @@
+"""Thin Python binding of libchem (ctypes).  Argument marshalling only: every
+step of the hot path runs in the library's HIP kernels.  Torch tensors are
+used as device memory (their data pointers go through the C ABI) and the
+current torch stream is the default context stream.
+
+The library must be built (``python -m paper_2510_23993_amd.build`` or
+``__graft_entry__.build()``); importing this module without it raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import List, Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "lib", "libchem.so")
+
+CHEM_OK, CHEM_W_INCOMPLETE = 0, 1
+ST_DONE, ST_SKIPPED, ST_KMAX, ST_FAIL, ST_TINV, ST_SURR_OK, ST_SURR_REJ = range(7)
+
+
+class chem_stats(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in (
+        "ncell", "n_active0", "n_active_after_bulk", "n_bulk_rounds", "n_sparse", "n_incomplete",
+        "n_fallback", "steps_total", "attempts_total", "rhs_evals", "jac_evals", "lu_facts",
+        "lin_solves", "max_steps_cell")] + [("t_total_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class chem_box(C.Structure):
+    _fields_ = [("ncell", C.c_int64), ("rho", C.c_void_p), ("e", C.c_void_p), ("Y", C.c_void_p),
+                ("ldY", C.c_int64), ("T", C.c_void_p), ("mask", C.c_void_p), ("status", C.c_void_p),
+                ("dt", C.c_double), ("level", C.c_int)]
+
+
+class ChemError(RuntimeError):
+    def __init__(self, rc, msg):
+        super().__init__(f"libchem error {rc}: {msg}")
+        self.rc = rc
+
+
+_lib = None
+
+EXPORTS = ["chem_load_mechanism", "chem_mech_info", "chem_species_name", "chem_free_mechanism",
+           "chem_ctx_create", "chem_ctx_destroy", "chem_set_option", "chem_get_option",
+           "chem_load_surrogate", "chem_integrate", "chem_integrate_boxes", "chem_prepare_state",
+           "chem_eval_rhs", "chem_synchronize", "chem_last_error"]
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libchem.so not built ({LIB_PATH}); run paper_2510_23993_amd/build.py")
+    # One HIP runtime per process: torch ships its own libamdhip64 (soname
+    # libamdhip64.so.7) and its libraries request it by the unversioned name.
+    # Loading torch first makes libchem's libamdhip64.so.7 dependency resolve
+    # to that already-loaded runtime, so device pointers and streams are shared.
+    import torch  # noqa: F401
+    L = C.CDLL(LIB_PATH)
+    vp, i64, dbl = C.c_void_p, C.c_int64, C.c_double
+    L.chem_last_error.restype = C.c_char_p
+    L.chem_load_mechanism.argtypes = [C.c_char_p, C.POINTER(vp)]
+    L.chem_mech_info.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.POINTER(dbl))]
+    L.chem_species_name.argtypes = [vp, C.c_int, C.POINTER(C.c_char_p)]
+    L.chem_free_mechanism.argtypes = [vp]
+    L.chem_free_mechanism.restype = None
+    L.chem_ctx_create.argtypes = [vp, C.c_int, vp, C.POINTER(vp)]
+    L.chem_ctx_destroy.argtypes = [vp]
+    L.chem_ctx_destroy.restype = None
+    L.chem_set_option.argtypes = [vp, C.c_char_p, dbl]
+    L.chem_get_option.argtypes = [vp, C.c_char_p, C.POINTER(dbl)]
+    L.chem_load_surrogate.argtypes = [vp, C.c_char_p]
+    L.chem_integrate.argtypes = [vp, i64, vp, vp, vp, i64, vp, vp, vp, dbl, dbl, dbl,
+                                 C.POINTER(chem_stats)]
+    L.chem_integrate_boxes.argtypes = [vp, C.c_int, C.POINTER(chem_box), dbl, dbl, C.POINTER(chem_stats)]
+    L.chem_prepare_state.argtypes = [vp, i64, vp, vp, vp, i64, vp, vp]
+    L.chem_eval_rhs.argtypes = [vp, i64, vp, vp, vp, vp]
+    L.chem_synchronize.argtypes = [vp]
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc < 0:
+        raise ChemError(rc, lib().chem_last_error().decode())
+    return rc
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _check_f64(name, t, shape):
+    import torch
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+class Mechanism:
+    def __init__(self, path: str):
+        h = C.c_void_p()
+        _check(lib().chem_load_mechanism(path.encode(), C.byref(h)))
+        self._h = h
+        ns, nr = C.c_int(), C.c_int()
+        W = C.POINTER(C.c_double)()
+        _check(lib().chem_mech_info(h, C.byref(ns), C.byref(nr), C.byref(W)))
+        self.ns, self.nr = ns.value, nr.value
+        self.W = [W[k] for k in range(self.ns)]
+        self.species = []
+        for k in range(self.ns):
+            nm = C.c_char_p()
+            _check(lib().chem_species_name(h, k, C.byref(nm)))
+            self.species.append(nm.value.decode())
+
+    def __del__(self):
+        try:
+            if self._h:
+                lib().chem_free_mechanism(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+
+class Context:
+    """Device workspace + stream binding for one mechanism."""
+
+    def __init__(self, mech: Mechanism, device: int = 0, stream=None, **options):
+        import torch
+        self.mech = mech
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = C.c_void_p()
+        _check(lib().chem_ctx_create(mech._h, device, C.c_void_p(stream.cuda_stream), C.byref(h)))
+        self._h = h
+        for k, v in options.items():
+            self.set_option(k, v)
+
+    def __del__(self):
+        try:
+            if self._h:
+                lib().chem_ctx_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+    def set_option(self, key: str, value: float):
+        _check(lib().chem_set_option(self._h, key.encode(), float(value)))
+
+    def get_option(self, key: str) -> float:
+        v = C.c_double()
+        _check(lib().chem_get_option(self._h, key.encode(), C.byref(v)))
+        return v.value
+
+    def integrate(self, rho, e, Y, T, dt, rtol, atol, mask=None, status=None, stats=True):
+        """rho, e, T: [n] float64 device tensors; Y: [ns, n] (column-major per
+        species, i.e. a contiguous [ns][n] tensor).  Y and T are updated in
+        place.  Returns the stats dict (synchronising) or None."""
+        n = rho.shape[0]
+        _check_f64("rho", rho, (n,))
+        _check_f64("e", e, (n,))
+        _check_f64("T", T, (n,))
+        _check_f64("Y", Y, (self.mech.ns, n))
+        st = chem_stats() if stats else None
+        rc = _check(lib().chem_integrate(self._h, n, _ptr(rho), _ptr(e), _ptr(Y), n, _ptr(T),
+                                         _ptr(mask), _ptr(status), float(dt), float(rtol),
+                                         float(atol), C.byref(st) if st is not None else None))
+        if st is None:
+            return None
+        d = st.as_dict()
+        d["rc"] = rc
+        return d
+
+    def integrate_boxes(self, boxes: Sequence[dict], rtol, atol, stats=True):
+        """boxes: dicts with rho, e, Y ([ns, n]), T, dt and optional mask,
+        status, level."""
+        arr = (chem_box * len(boxes))()
+        for i, b in enumerate(boxes):
+            n = b["rho"].shape[0]
+            _check_f64("Y", b["Y"], (self.mech.ns, n))
+            arr[i] = chem_box(n, _ptr(b["rho"]), _ptr(b["e"]), _ptr(b["Y"]), n, _ptr(b["T"]),
+                              _ptr(b.get("mask")), _ptr(b.get("status")), float(b["dt"]),
+                              int(b.get("level", 0)))
+        st = chem_stats() if stats else None
+        rc = _check(lib().chem_integrate_boxes(self._h, len(boxes), arr, float(rtol), float(atol),
+                                               C.byref(st) if st is not None else None))
+        if st is None:
+            return None
+        d = st.as_dict()
+        d["rc"] = rc
+        return d
+
+    def prepare_state(self, T, p, Y, rho, e):
+        n = T.shape[0]
+        _check(lib().chem_prepare_state(self._h, n, _ptr(T), _ptr(p), _ptr(Y), n, _ptr(rho), _ptr(e)))
+
+    def eval_rhs(self, rho, y, f, J=None):
+        n = rho.shape[0]
+        _check(lib().chem_eval_rhs(self._h, n, _ptr(rho), _ptr(y), _ptr(f), _ptr(J)))
+
+    def synchronize(self):
+        _check(lib().chem_synchronize(self._h))

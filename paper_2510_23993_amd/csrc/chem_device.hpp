@@ -1,0 +1,464 @@
+// Device building blocks for one reactor cell per lane (gfx950, FP64):
+// NASA-7 thermo, log-form (matrix) rates of progress, the reactor
+// right-hand side, its analytic Jacobian, an LU with partial pivoting kept
+// in LDS, and the temperature inversion.  Templated on a generated
+// mechanism-structure type M (species indices and stoichiometry are
+// compile-time constants; numbers come from Params<M> in device memory).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "chem_types.hpp"
+
+namespace chem {
+
+// ---------------------------------------------------------------- thermo
+// NASA-7 with pre-divided coefficients (host packs them):
+//   h/RT = H0 + T(H1 + T(H2 + T(H3 + T H4))) + H5/T
+//   s/R  = S0 lnT + T(S1 + T(S2 + T(S3 + T S4))) + S5
+//   cp/R = C0 + T(C1 + T(C2 + T(C3 + T C4)))
+// The low set applies iff T < Tmid (the polynomials are not clamped).
+template <class M>
+__device__ __forceinline__ void thermo_hg(const Params<M>& P, double T, double lnT, double invT,
+                                          double* h_RT, double* g_RT) {
+#pragma unroll
+    for (int k = 0; k < M::NS; k++) {
+        const bool lo = T < P.Tmid[k];
+        double H[6], S[6];
+#pragma unroll
+        for (int a = 0; a < 6; a++) {
+            H[a] = lo ? P.hlo[k][a] : P.hhi[k][a];
+            S[a] = lo ? P.slo[k][a] : P.shi[k][a];
+        }
+        const double h = H[0] + T * (H[1] + T * (H[2] + T * (H[3] + T * H[4]))) + H[5] * invT;
+        const double s = S[0] * lnT + T * (S[1] + T * (S[2] + T * (S[3] + T * S[4]))) + S[5];
+        h_RT[k] = h;
+        g_RT[k] = h - s;
+    }
+}
+
+template <class M>
+__device__ __forceinline__ double cp_R(const Params<M>& P, int k, double T) {
+    const bool lo = T < P.Tmid[k];
+    double c[5];
+#pragma unroll
+    for (int a = 0; a < 5; a++) c[a] = lo ? P.clo[k][a] : P.chi[k][a];
+    return c[0] + T * (c[1] + T * (c[2] + T * (c[3] + T * c[4])));
+}
+
+template <class M>
+__device__ __forceinline__ double dcp_R_dT(const Params<M>& P, int k, double T) {
+    const bool lo = T < P.Tmid[k];
+    double c[5];
+#pragma unroll
+    for (int a = 0; a < 5; a++) c[a] = lo ? P.clo[k][a] : P.chi[k][a];
+    return c[1] + T * (2.0 * c[2] + T * (3.0 * c[3] + T * 4.0 * c[4]));
+}
+
+template <class M>
+__device__ __forceinline__ double h_RT_one(const Params<M>& P, int k, double T, double invT) {
+    const bool lo = T < P.Tmid[k];
+    double H[6];
+#pragma unroll
+    for (int a = 0; a < 6; a++) H[a] = lo ? P.hlo[k][a] : P.hhi[k][a];
+    return H[0] + T * (H[1] + T * (H[2] + T * (H[3] + T * H[4]))) + H[5] * invT;
+}
+
+// e(T, Y) and c_v(T, Y), mass based
+template <class M>
+__device__ __forceinline__ void e_cv(const Params<M>& P, double T, const double* Y, double& e,
+                                     double& cv) {
+    const double invT = 1.0 / T;
+    double se = 0.0, sc = 0.0;
+#pragma unroll
+    for (int k = 0; k < M::NS; k++) {
+        const double w = Y[k] * P.invW[k];
+        se += w * (h_RT_one(P, k, T, invT) - 1.0);
+        sc += w * (cp_R(P, k, T) - 1.0);
+    }
+    e = se * RGAS * T;
+    cv = sc * RGAS;
+}
+
+// Newton on e(T, Y) = e0 with a bisection guard in [100, 6000] K.
+// Returns false if e0 is outside [e(100), e(6000)].
+template <class M>
+__device__ bool T_from_e(const Params<M>& P, double e0, const double* Y, double Tg, double& Tout) {
+    double lo = 100.0, hi = 6000.0, elo, ehi, cv;
+    e_cv(P, lo, Y, elo, cv);
+    e_cv(P, hi, Y, ehi, cv);
+    if (!(elo <= e0 && ehi >= e0)) return false;
+    double T = (Tg > lo && Tg < hi) ? Tg : 1500.0;
+    for (int it = 0; it < 100; it++) {
+        double e;
+        e_cv(P, T, Y, e, cv);
+        const double fT = e - e0;
+        if (fT == 0.0) break;
+        if (fT < 0.0) lo = T;
+        else hi = T;
+        double Tn = T - fT / cv;
+        if (!(Tn > lo && Tn < hi)) Tn = 0.5 * (lo + hi);
+        const double dT = fabs(Tn - T);
+        T = Tn;
+        if (dT <= 1e-12 * T || hi - lo <= 1e-12 * T) break;
+    }
+    Tout = T;
+    return true;
+}
+
+// --------------------------------------------------------------- kinetics
+constexpr double LN10 = 2.302585092994045684;
+constexpr double INV_LN10 = 0.434294481903251828;
+constexpr double LN_PREF_OVER_R = 9.408091968961747;  // ln(101325 / 8.314462618)
+
+// Per-reaction log-space quantities: ln kf (falloff included) and, for
+// falloff reactions, d ln kf / d ln [M] and d ln kf / dT.
+struct RxnK {
+    double lnkf, dlnkf_dT, dlnkf_dlnM, M;
+};
+
+template <class M, int j>
+__device__ __forceinline__ void rxn_k(const Params<M>& P, double lnT, double invT, const double* C,
+                                      RxnK& r, bool want_deriv) {
+    constexpr int TY = M::TYPE[j];
+    // Arrhenius as a contraction of (ln A, b, Ea/R) with (1, ln T, -1/T)
+    double lnkinf = P.lnA[j] + P.b[j] * lnT - P.EaR[j] * invT;
+    double dlnkinf = (P.b[j] + P.EaR[j] * invT) * invT;
+    r.M = 0.0;
+    if (TY != RX_ELEM) {
+#pragma unroll
+        for (int k = 0; k < M::NS; k++) r.M += P.eff[j][k] * C[k];
+    }
+    r.lnkf = lnkinf;
+    r.dlnkf_dT = dlnkinf;
+    r.dlnkf_dlnM = 0.0;
+    if (TY == RX_FO) {
+        const double lnk0 = P.lnA0[j] + P.b0[j] * lnT - P.Ea0R[j] * invT;
+        const double dlnk0 = (P.b0[j] + P.Ea0R[j] * invT) * invT;
+        const double Pr = fmax(exp(lnk0 - lnkinf) * r.M, 1e-300);
+        const double lnPr = log(Pr);
+        double lnF = 0.0, dlnF_dlnPr = 0.0, dlnF_dT = 0.0;
+        if (M::TROE[j] > 0) {
+            const double a = P.troe[j][0], T = 1.0 / invT;
+            const double e3 = exp(-T / P.troe[j][1]), e1 = exp(-T / P.troe[j][2]);
+            double Fc = (1.0 - a) * e3 + a * e1;
+            double dFc = -(1.0 - a) / P.troe[j][1] * e3 - a / P.troe[j][2] * e1;
+            if (M::TROE[j] == 4) {
+                const double e2 = exp(-P.troe[j][3] * invT);
+                Fc += e2;
+                dFc += P.troe[j][3] * invT * invT * e2;
+            }
+            const double phi = log(Fc) * INV_LN10;
+            const double c = -0.4 - 0.67 * phi, nn = 0.75 - 1.27 * phi;
+            const double u = lnPr * INV_LN10 + c;
+            const double den = nn - 0.14 * u;
+            const double f1 = u / den;
+            const double q = 1.0 + f1 * f1;
+            lnF = LN10 * phi / q;
+            if (want_deriv) {
+                const double iq2 = 1.0 / (q * q), iden2 = 1.0 / (den * den);
+                const double df1_dx = nn * iden2;
+                const double df1_dphi = (-0.67 * den + u * (1.27 - 0.14 * 0.67)) * iden2;
+                dlnF_dlnPr = -phi * 2.0 * f1 * df1_dx * iq2;
+                const double dlog10F_dphi = 1.0 / q - phi * 2.0 * f1 * df1_dphi * iq2;
+                dlnF_dT = dlog10F_dphi * dFc / Fc;
+            }
+        }
+        const double ip = 1.0 / (1.0 + Pr);
+        r.lnkf = lnkinf + lnPr + log(ip) + lnF;   // ln(kinf Pr/(1+Pr) F)
+        if (want_deriv) {
+            const double dlnPr_dT = dlnk0 - dlnkinf;
+            r.dlnkf_dlnM = ip + dlnF_dlnPr;
+            r.dlnkf_dT = dlnkinf + dlnPr_dT * ip + dlnF_dT + dlnF_dlnPr * dlnPr_dT;
+        }
+    }
+}
+
+// Shared per-cell quantities for one evaluation.
+template <class M>
+struct CellEval {
+    double C[M::NS], lnC[M::NS], h_RT[M::NS], g_RT[M::NS];
+    double lnT, invT, lnPref;
+};
+
+template <class M>
+__device__ __forceinline__ void cell_eval(const Params<M>& P, double rho, const double* y,
+                                          CellEval<M>& E) {
+    const double T = y[M::NS];
+    E.lnT = log(T);
+    E.invT = 1.0 / T;
+    E.lnPref = LN_PREF_OVER_R - E.lnT;
+#pragma unroll
+    for (int k = 0; k < M::NS; k++) {
+        E.C[k] = rho * y[k] * P.invW[k];
+        E.lnC[k] = log(fmax(E.C[k], C_FLOOR));
+    }
+    thermo_hg(P, T, E.lnT, E.invT, E.h_RT, E.g_RT);
+}
+
+// ln qf and ln qr of reaction j: stoichiometric contractions against ln C
+// (forward: nu'; reverse: nu'' minus the ln Kc row).
+template <class M, int j>
+__device__ __forceinline__ void rxn_lnq(const CellEval<M>& E, double lnkf, double& lnqf,
+                                        double& lnqr) {
+    lnqf = lnkf;
+#pragma unroll
+    for (int i = 0; i < M::NRE[j]; i++) lnqf += M::RNU[j][i] * E.lnC[M::RSP[j][i]];
+    lnqr = -1e300;
+    if (M::REV[j]) {
+        double sg = 0.0;  // sum_k nu_kj g_k/RT
+#pragma unroll
+        for (int i = 0; i < M::NPR[j]; i++) sg += M::PNU[j][i] * E.g_RT[M::PSP[j][i]];
+#pragma unroll
+        for (int i = 0; i < M::NRE[j]; i++) sg -= M::RNU[j][i] * E.g_RT[M::RSP[j][i]];
+        const double lnKc = -sg + M::DNU[j] * E.lnPref;
+        lnqr = lnkf - lnKc;
+#pragma unroll
+        for (int i = 0; i < M::NPR[j]; i++) lnqr += M::PNU[j][i] * E.lnC[M::PSP[j][i]];
+    }
+}
+
+template <class M, int j>
+__device__ __forceinline__ void rhs_loop(const Params<M>& P, const CellEval<M>& E, double* om) {
+    if constexpr (j < M::NR) {
+        RxnK r;
+        rxn_k<M, j>(P, E.lnT, E.invT, E.C, r, false);
+        double lnqf, lnqr;
+        rxn_lnq<M, j>(E, r.lnkf, lnqf, lnqr);
+        double q = exp(lnqf);
+        if (M::REV[j]) q -= exp(lnqr);
+        if (M::TYPE[j] == RX_TB) q *= r.M;
+#pragma unroll
+        for (int i = 0; i < M::NRE[j]; i++) om[M::RSP[j][i]] -= M::RNU[j][i] * q;
+#pragma unroll
+        for (int i = 0; i < M::NPR[j]; i++) om[M::PSP[j][i]] += M::PNU[j][i] * q;
+        // keep the scheduler from interleaving reactions (live ranges of the
+        // inline exp/log sequences would otherwise overflow the register file)
+        __builtin_amdgcn_sched_barrier(0);
+        rhs_loop<M, j + 1>(P, E, om);
+    }
+}
+
+// f = dy/dt for y = (Y_1..Y_NS, T) at constant rho and e.
+template <class M>
+__device__ void rhs(const Params<M>& P, double rho, const double* y, double* f) {
+    CellEval<M> E;
+    cell_eval(P, rho, y, E);
+    double om[M::NS];
+#pragma unroll
+    for (int k = 0; k < M::NS; k++) om[k] = 0.0;
+    rhs_loop<M, 0>(P, E, om);
+    const double T = y[M::NS];
+    double cvs = 0.0, S = 0.0;
+    const double irho = 1.0 / rho;
+#pragma unroll
+    for (int k = 0; k < M::NS; k++) {
+        f[k] = P.W[k] * om[k] * irho;
+        cvs += y[k] * P.invW[k] * (cp_R(P, k, T) - 1.0);
+        S += (E.h_RT[k] - 1.0) * om[k];
+    }
+    // -sum u_k om_k/(rho cv) with u_k = (h_RT - 1) R T and cv = R cvs
+    f[M::NS] = -S * T * irho / cvs;
+}
+
+// ---------------------------------------------------------------- Jacobian
+// The species rows J[k][m] = (W_k/W_m) sum_j nu_kj dq_j/dC_m are accumulated
+// entry by entry through acc(k, m, v) (into the lane's LDS Newton matrix in
+// the integrator), so no dense d(omega)/dC block is held in registers.  The
+// temperature row needs dSm[m] = sum_k u_k d omega_k/dC_m, om and dwT, which
+// are kept as NS-vectors.
+template <class M, int j, class Acc>
+__device__ __forceinline__ void jac_loop(const Params<M>& P, const CellEval<M>& E, const double* invC,
+                                         const double* uk, double* om, double* dwT, double* dSm,
+                                         Acc& acc) {
+    if constexpr (j < M::NR) {
+        constexpr int TY = M::TYPE[j];
+        RxnK r;
+        rxn_k<M, j>(P, E.lnT, E.invT, E.C, r, true);
+        double lnqf, lnqr;
+        rxn_lnq<M, j>(E, r.lnkf, lnqf, lnqr);
+        const double qf = exp(lnqf);
+        const double qr = M::REV[j] ? exp(lnqr) : 0.0;
+        const double mul = (TY == RX_TB) ? r.M : 1.0;
+        const double net = qf - qr;
+        // d ln qf/dT = dlnkf, d ln qr/dT = dlnkf - dlnKc
+        double dlnKc = 0.0;
+        if (M::REV[j]) {
+            double sh = 0.0;
+#pragma unroll
+            for (int i = 0; i < M::NPR[j]; i++) sh += M::PNU[j][i] * E.h_RT[M::PSP[j][i]];
+#pragma unroll
+            for (int i = 0; i < M::NRE[j]; i++) sh -= M::RNU[j][i] * E.h_RT[M::RSP[j][i]];
+            dlnKc = (sh - M::DNU[j]) * E.invT;
+        }
+        const double dqdT = mul * (qf * r.dlnkf_dT - qr * (r.dlnkf_dT - dlnKc));
+        const double q = mul * net;
+        // dense part of dq/dC_m (alpha_m g) from the third-body concentration
+        double g = 0.0;
+        if (TY == RX_TB) g = net;
+        if (TY == RX_FO) g = net * r.dlnkf_dlnM / fmax(r.M, 1e-300);
+        // participant k with signed coefficient s (negative for reactants)
+        auto row = [&](int k, double s) {
+            om[k] += s * q;
+            dwT[k] += s * dqdT;
+#pragma unroll
+            for (int i = 0; i < M::NRE[j]; i++) {
+                const int m = M::RSP[j][i];
+                const double v = s * mul * M::RNU[j][i] * qf * invC[m];
+                acc(k, m, P.W[k] * P.invW[m] * v);
+                dSm[m] += uk[k] * v;
+            }
+#pragma unroll
+            for (int i = 0; i < M::NPR[j]; i++) {
+                const int m = M::PSP[j][i];
+                const double v = -s * mul * M::PNU[j][i] * qr * invC[m];
+                acc(k, m, P.W[k] * P.invW[m] * v);
+                dSm[m] += uk[k] * v;
+            }
+            if (TY != RX_ELEM) {
+#pragma unroll
+                for (int m = 0; m < M::NS; m++) {
+                    const double v = s * P.eff[j][m] * g;
+                    acc(k, m, P.W[k] * P.invW[m] * v);
+                    dSm[m] += uk[k] * v;
+                }
+            }
+        };
+#pragma unroll
+        for (int i = 0; i < M::NRE[j]; i++) row(M::RSP[j][i], -(double)M::RNU[j][i]);
+#pragma unroll
+        for (int i = 0; i < M::NPR[j]; i++) row(M::PSP[j][i], (double)M::PNU[j][i]);
+        __builtin_amdgcn_sched_barrier(0);
+        jac_loop<M, j + 1>(P, E, invC, uk, om, dwT, dSm, acc);
+    }
+}
+
+// Analytic Jacobian of the reactor RHS.  acc(i, j, v) adds v to entry (i, j)
+// of the species rows (called several times per entry); put(i, j, v) sets the
+// last column and the temperature row once per entry.
+template <class M, class Acc, class Put>
+__device__ __forceinline__ void jac_eval(const Params<M>& P, double rho, const double* y, Acc& acc,
+                                         Put put) {
+    constexpr int NS = M::NS;
+    CellEval<M> E;
+    cell_eval(P, rho, y, E);
+    const double T = y[NS];
+    double invC[NS], uk[NS], om[NS], dwT[NS], dSm[NS];
+#pragma unroll
+    for (int k = 0; k < NS; k++) {
+        invC[k] = 1.0 / fmax(E.C[k], C_FLOOR);
+        uk[k] = (E.h_RT[k] - 1.0) * T;  // u_k / R (molar)
+        om[k] = dwT[k] = dSm[k] = 0.0;
+    }
+    jac_loop<M, 0>(P, E, invC, uk, om, dwT, dSm, acc);
+    const double irho = 1.0 / rho;
+    double cvs = 0.0, dcvs = 0.0, S = 0.0, cvk[NS];
+#pragma unroll
+    for (int k = 0; k < NS; k++) {
+        cvk[k] = cp_R(P, k, T) - 1.0;   // c_v,k / R (molar)
+        cvs += y[k] * P.invW[k] * cvk[k];
+        dcvs += y[k] * P.invW[k] * dcp_R_dT(P, k, T);
+        S += uk[k] * om[k];
+    }
+    const double fT = -S * irho / cvs;
+#pragma unroll
+    for (int k = 0; k < NS; k++) put(k, NS, P.W[k] * irho * dwT[k]);
+    // temperature row: dT/dt = -sum u_k om_k / (rho c_v), dC_m/dY_m = rho/W_m
+#pragma unroll
+    for (int m = 0; m < NS; m++) put(NS, m, -P.invW[m] / cvs * (dSm[m] + fT * cvk[m]));
+    double dS = 0.0;
+#pragma unroll
+    for (int k = 0; k < NS; k++) dS += cvk[k] * om[k] + uk[k] * dwT[k];
+    put(NS, NS, -dS * irho / cvs - fT * dcvs / cvs);
+}
+
+// Newton matrix A = I - c J written to LDS (element (r, c) at A[(r*N + c)*64]).
+template <class M>
+__device__ __forceinline__ void newton_matrix(const Params<M>& P, double rho, const double* y,
+                                              double c, double* A) {
+    constexpr int N = M::N, NS = M::NS;
+#pragma unroll
+    for (int r = 0; r < NS; r++)
+#pragma unroll
+        for (int q = 0; q < NS; q++) A[(r * N + q) * 64] = (r == q) ? 1.0 : 0.0;
+    auto acc = [&](int i, int j, double v) { A[(i * N + j) * 64] -= c * v; };
+    jac_eval<M>(P, rho, y, acc, [&](int i, int j, double v) {
+        A[(i * N + j) * 64] = (i == j ? 1.0 : 0.0) - c * v;
+    });
+}
+
+// --------------------------------------------------------------- dense LU
+// In-place LU with partial pivoting of the lane's N x N matrix in LDS
+// (element (r, c) at A[(r*N + c)*64]).  The diagonal is replaced by its
+// reciprocal; pivot rows go to piv[].  Rows are swapped only from column k
+// on, and solves replay the same sequence of interchanges.  Returns false
+// if a pivot is zero or not finite.
+template <int N>
+__device__ bool lu_factor(double* A, int* piv) {
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < N; k++) {
+        int p = k;
+        double best = fabs(A[(k * N + k) * 64]);
+#pragma unroll
+        for (int i = k + 1; i < N; i++) {
+            const double v = fabs(A[(i * N + k) * 64]);
+            if (v > best) {
+                best = v;
+                p = i;
+            }
+        }
+        piv[k] = p;
+        if (!(best > 0.0) || !isfinite(best)) ok = false;
+        if (p != k) {
+#pragma unroll
+            for (int c = k; c < N; c++) {
+                const double t = A[(k * N + c) * 64];
+                A[(k * N + c) * 64] = A[(p * N + c) * 64];
+                A[(p * N + c) * 64] = t;
+            }
+        }
+        double rowk[N];
+#pragma unroll
+        for (int c = k; c < N; c++) rowk[c] = A[(k * N + c) * 64];
+        const double inv = 1.0 / rowk[k];
+        A[(k * N + k) * 64] = inv;
+#pragma unroll
+        for (int i = k + 1; i < N; i++) {
+            const double l = A[(i * N + k) * 64] * inv;
+            A[(i * N + k) * 64] = l;
+#pragma unroll
+            for (int c = k + 1; c < N; c++) A[(i * N + c) * 64] -= l * rowk[c];
+        }
+    }
+    return ok;
+}
+
+template <int N>
+__device__ __forceinline__ void lu_solve(const double* A, const int* piv, double* b) {
+#pragma unroll
+    for (int k = 0; k < N; k++) {
+        // interchange b[k] <-> b[piv[k]] (piv[k] >= k) with selects: b stays in registers
+        const int p = piv[k];
+#pragma unroll
+        for (int i = k + 1; i < N; i++) {
+            const bool s = (p == i);
+            const double bk = b[k], bi = b[i];
+            b[k] = s ? bi : bk;
+            b[i] = s ? bk : bi;
+        }
+        const double bk = b[k];
+#pragma unroll
+        for (int i = k + 1; i < N; i++) b[i] -= A[(i * N + k) * 64] * bk;
+    }
+#pragma unroll
+    for (int i = N - 1; i >= 0; i--) {
+        double s = b[i];
+#pragma unroll
+        for (int c = i + 1; c < N; c++) s -= A[(i * N + c) * 64] * b[c];
+        b[i] = s * A[(i * N + i) * 64];
+    }
+}
+
+}  // namespace chem

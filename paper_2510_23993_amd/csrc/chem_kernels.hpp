@@ -1,0 +1,723 @@
+// Kernels of the chemistry hot path (gfx950, wave64).  One reactor cell per
+// lane; the per-lane Newton matrix / LU lives in LDS, the BDF backward
+// differences in a per-lane global workspace slot (coalesced: lane-major).
+//
+// Pipeline of the bulk-sparse algorithm (Alg. 3):
+//   k_screen    T from (e, Y), skip cold / masked cells, per-block counts
+//   k_scan      exclusive scan of the block counts (one workgroup)
+//   k_scatter   deterministic compaction of active cells -> active_ids
+//   k_integrate<BULK>    up to kmax_bulk steps per cell per round; gated on
+//                        the device while more than nactive_star cells remain
+//   k_count_unfinished / k_scan / k_scatter_unfinished -> sparse slot list
+//   k_integrate<SPARSE>  persistent kernel: lanes pull cells from a queue and
+//                        integrate them to completion
+// The plain algorithm (Alg. 2) is k_screen + k_integrate<PLAIN>: one thread
+// per cell, integrate to completion, no refill.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "chem_device.hpp"
+
+namespace chem {
+
+enum Mode { PLAIN = 0, BULK = 1, SPARSE = 2 };
+
+__device__ __forceinline__ int find_box(const DevBox* boxes, int nbox, int64_t g) {
+    int lo = 0, hi = nbox - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (boxes[mid].off <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ unsigned long long wave_ballot(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// --------------------------------------------------------------- utilities
+__global__ void k_fill_u8(uint8_t* p, int64_t n, uint8_t v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void k_fill_i32(int* p, int64_t n, int v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void k_fill_u64(unsigned long long* p, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0ull;
+}
+
+// block of 256 threads = 4 waves; returns the block total in every thread and
+// each thread's exclusive prefix within the block.
+__device__ __forceinline__ int block_prefix_256(bool pred, int* sh, int& total) {
+    const unsigned long long m = wave_ballot(pred);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int within = __popcll(m & ((1ull << lane) - 1ull));
+    if (lane == 0) sh[w] = __popcll(m);
+    __syncthreads();
+    int before = 0;
+    total = 0;
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        if (i < w) before += sh[i];
+        total += sh[i];
+    }
+    __syncthreads();
+    return before + within;
+}
+
+// One workgroup of 1024 threads: exclusive scan of cnt[0..nb) into off[],
+// total into *total.
+__global__ void __launch_bounds__(1024) k_scan(const int* __restrict__ cnt, int nb,
+                                               int* __restrict__ off, int* __restrict__ total) {
+    __shared__ int part[1024];
+    const int t = threadIdx.x;
+    const int per = (nb + 1023) / 1024;
+    const int b0 = t * per, b1 = min(nb, b0 + per);
+    int s = 0;
+    for (int i = b0; i < b1; i++) s += cnt[i];
+    part[t] = s;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {   // Hillis-Steele inclusive scan of the partials
+        const int v = (t >= d) ? part[t - d] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int run = part[t] - s;
+    for (int i = b0; i < b1; i++) {
+        off[i] = run;
+        run += cnt[i];
+    }
+    if (t == 1023) *total = part[1023];
+}
+
+// --------------------------------------------------------------- screening
+// status_int[g] <- ST_ACTIVE for cells to integrate, else a final code.
+// T[i] <- T0 = T(e, Y) for every cell with a valid state.
+template <class M>
+__global__ void __launch_bounds__(256) k_screen(const Params<M>* __restrict__ Pp,
+                                                const DevBox* __restrict__ boxes, int nbox,
+                                                int64_t total, double t_react_min,
+                                                uint8_t* __restrict__ st_int,
+                                                int* __restrict__ block_cnt) {
+    __shared__ int sh[4];
+    const Params<M>& P = *Pp;
+    const int64_t g = blockIdx.x * 256ll + threadIdx.x;
+    bool active = false;
+    if (g < total) {
+        const DevBox& B = boxes[find_box(boxes, nbox, g)];
+        const int64_t i = g - B.off;
+        uint8_t st;
+        if (B.mask && B.mask[i]) {
+            st = ST_SKIPPED;
+        } else {
+            const double rho = B.rho[i], e = B.e[i];
+            double Y[M::NS];
+#pragma unroll
+            for (int k = 0; k < M::NS; k++) Y[k] = B.Y[k * B.ldY + i];
+            double T0;
+            if (!(rho > 0.0) || !isfinite(rho) || !isfinite(e) || !T_from_e(P, e, Y, B.T[i], T0)) {
+                st = ST_TINV;
+            } else {
+                B.T[i] = T0;
+                st = (T0 < t_react_min) ? ST_SKIPPED : ST_ACTIVE;
+            }
+        }
+        st_int[g] = st;
+        if (st != ST_ACTIVE && B.status) B.status[i] = st;
+        active = (st == ST_ACTIVE);
+    }
+    int tot;
+    block_prefix_256(active, sh, tot);
+    if (threadIdx.x == 0) block_cnt[blockIdx.x] = tot;
+}
+
+// active_ids[off[b] + rank] = g for ST_ACTIVE cells, in increasing g.
+__global__ void __launch_bounds__(256) k_scatter(const uint8_t* __restrict__ st_int, int64_t total,
+                                                 const int* __restrict__ off,
+                                                 int* __restrict__ ids) {
+    __shared__ int sh[4];
+    const int64_t g = blockIdx.x * 256ll + threadIdx.x;
+    const bool a = g < total && st_int[g] == ST_ACTIVE;
+    int tot;
+    const int r = block_prefix_256(a, sh, tot);
+    if (a) ids[off[blockIdx.x] + r] = (int)g;
+}
+
+// unfinished slots (flag != 2) among [0, *n)
+__global__ void __launch_bounds__(256) k_count_unfinished(const uint8_t* __restrict__ flag,
+                                                          const int* __restrict__ n,
+                                                          int* __restrict__ block_cnt) {
+    __shared__ int sh[4];
+    const int64_t s = blockIdx.x * 256ll + threadIdx.x;
+    const bool a = s < *n && flag[s] != 2;
+    int tot;
+    block_prefix_256(a, sh, tot);
+    if (threadIdx.x == 0) block_cnt[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(256) k_scatter_unfinished(const uint8_t* __restrict__ flag,
+                                                            const int* __restrict__ n,
+                                                            const int* __restrict__ off,
+                                                            int* __restrict__ ids) {
+    __shared__ int sh[4];
+    const int64_t s = blockIdx.x * 256ll + threadIdx.x;
+    const bool a = s < *n && flag[s] != 2;
+    int tot;
+    const int r = block_prefix_256(a, sh, tot);
+    if (a) ids[off[blockIdx.x] + r] = (int)s;
+}
+
+// --------------------------------------------------------- state preparation
+template <class M>
+__global__ void k_prepare(const Params<M>* __restrict__ Pp, int64_t n, const double* __restrict__ T,
+                          const double* __restrict__ p, const double* __restrict__ Y, int64_t ldY,
+                          double* __restrict__ rho, double* __restrict__ e) {
+    const Params<M>& P = *Pp;
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double y[M::NS], sw = 0.0;
+#pragma unroll
+    for (int k = 0; k < M::NS; k++) {
+        y[k] = Y[k * ldY + i];
+        sw += y[k] * P.invW[k];
+    }
+    double ee, cv;
+    e_cv(P, T[i], y, ee, cv);
+    rho[i] = p[i] / (RGAS * T[i] * sw);
+    e[i] = ee;
+}
+
+template <class M>
+__global__ void k_eval_rhs(const Params<M>* __restrict__ Pp, int64_t n, const double* __restrict__ rho,
+                           const double* __restrict__ y, double* __restrict__ f,
+                           double* __restrict__ J) {
+    const Params<M>& P = *Pp;
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    double yy[M::N], ff[M::N];
+#pragma unroll
+    for (int i = 0; i < M::N; i++) yy[i] = y[i * n + c];
+    rhs(P, rho[c], yy, ff);
+#pragma unroll
+    for (int i = 0; i < M::N; i++) f[i * n + c] = ff[i];
+    if (J) {
+#pragma unroll
+        for (int i = 0; i < M::NS; i++)
+#pragma unroll
+            for (int j = 0; j < M::NS; j++) J[(i * M::N + j) * n + c] = 0.0;
+        auto acc = [&](int i, int j, double v) { J[(i * M::N + j) * n + c] += v; };
+        jac_eval<M>(P, rho[c], yy, acc, [&](int i, int j, double v) { J[(i * M::N + j) * n + c] = v; });
+    }
+}
+
+// ------------------------------------------------------------ BDF stepper
+// Variable-order (1-5) BDF in backward-difference form on a quasi-constant
+// step (Shampine & Reichelt 1997, kappa = 0): predictor y0 = sum_{j<=k} D_j,
+// correction d solving d = (h/gamma_k) f(y0 + d) - psi by modified Newton
+// with M = I - c_lu J (LU in LDS; J and LU refreshed together when the
+// step-size coefficient drifts by more than 30% or Newton fails with a
+// Jacobian from an earlier step), local error d/(k+1), WRMS norm with
+// weights 1/(rtol |y| + atol).  D lives in global memory: D(j, i) at
+// D[(j*N + i) * ld].
+
+__device__ __forceinline__ double gamma_k(int k) {  // sum_{i<=k} 1/i
+    double g = 0.0;
+    g = (k == 1) ? 1.0 : g;
+    g = (k == 2) ? 1.5 : g;
+    g = (k == 3) ? 11.0 / 6.0 : g;
+    g = (k == 4) ? 25.0 / 12.0 : g;
+    g = (k == 5) ? 137.0 / 60.0 : g;
+    return g;
+}
+
+template <class M>
+struct Lane {
+    static constexpr int N = M::N;
+    double t, tend, h, c_lu, rho;
+    int k, neq, att, round_att;
+    bool lu_ok, jac_fresh;
+    int piv[N];
+    // per-lane statistics
+    unsigned long long n_steps, n_att, n_rhs, n_jac, n_lu, n_solve;
+};
+
+template <int N>
+__device__ __forceinline__ double wrms(const double* v, const double* isc) {
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < N; i++) {
+        const double r = v[i] * isc[i];
+        s += r * r;
+    }
+    return sqrt(s * (1.0 / N));
+}
+
+// D_j <- nabla'^j P(t_n) on the grid of spacing rho*h (j = 1..k; D_0 unchanged):
+// T_ji = sum_m (-1)^m C(j,m) b_i(m rho), b_i(x) = prod_{l=1..i} (l - 1 - x)/l.
+template <int N>
+__device__ void rescale(double* D, int64_t ld, int k, double r) {
+    double Tm[MAXORD + 1][MAXORD + 1];
+#pragma unroll
+    for (int j = 1; j <= MAXORD; j++) {
+#pragma unroll
+        for (int i = 0; i <= MAXORD; i++) {
+            double s = 0.0, binom = 1.0;
+#pragma unroll
+            for (int m = 0; m <= j; m++) {
+                double b = 1.0;
+                const double x = m * r;
+#pragma unroll
+                for (int l = 1; l <= i; l++) b *= (l - 1 - x) * (1.0 / l);
+                s += ((m & 1) ? -binom : binom) * b;
+                binom = binom * (j - m) / (m + 1);
+            }
+            Tm[j][i] = s;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < N; c++) {
+        double d[MAXORD + 1];
+#pragma unroll
+        for (int i = 0; i <= MAXORD; i++) d[i] = (i <= k) ? D[(i * N + c) * ld] : 0.0;
+#pragma unroll
+        for (int j = 1; j <= MAXORD; j++) {
+            if (j <= k) {
+                double s = 0.0;
+#pragma unroll
+                for (int i = 0; i <= MAXORD; i++) s += Tm[j][i] * d[i];
+                D[(j * N + c) * ld] = s;
+            }
+        }
+    }
+}
+
+enum StepResult { SR_RETRY = 0, SR_ACCEPT = 1, SR_DONE = 2, SR_FAIL = 3 };
+
+template <class M>
+__device__ int bdf_attempt(const Params<M>& P, Lane<M>& L, double* D, int64_t ld, double* A,
+                           double rtol, double atol) {
+    constexpr int N = M::N;
+    constexpr double EPS = 2.220446049250313e-16;
+    L.att++;
+    L.round_att++;
+    L.n_att++;
+    if (!(L.h >= 10.0 * EPS * fabs(L.t))) return SR_FAIL;
+    bool last = false;
+    if (L.t + L.h >= L.tend) {
+        const double hn = L.tend - L.t;
+        rescale<N>(D, ld, L.k, hn / L.h);
+        L.h = hn;
+        L.neq = 0;
+        last = true;
+    }
+    const double tn = last ? L.tend : L.t + L.h;
+    const int k = L.k;
+    const double gk = gamma_k(k);
+    double yp[N], psi[N], isc[N];
+#pragma unroll
+    for (int i = 0; i < N; i++) {
+        double a = 0.0, b = 0.0, gj = 0.0;
+#pragma unroll
+        for (int j = 0; j <= MAXORD; j++) {
+            if (j <= k) {
+                const double dj = D[(j * N + i) * ld];
+                a += dj;
+                if (j >= 1) {
+                    gj += 1.0 / j;
+                    b += gj * dj;
+                }
+            }
+        }
+        yp[i] = a;
+        psi[i] = b / gk;
+        isc[i] = 1.0 / (atol + rtol * fabs(a));
+    }
+    const double c = L.h / gk;
+    if (!L.lu_ok || fabs(c - L.c_lu) > 0.3 * L.c_lu) {
+        newton_matrix<M>(P, L.rho, yp, c, A);
+        L.n_jac++;
+        L.n_lu++;
+        L.jac_fresh = true;
+        L.lu_ok = lu_factor<N>(A, L.piv);
+        L.c_lu = c;
+        if (!L.lu_ok) {   // singular even with a fresh Jacobian: shrink the step
+            rescale<N>(D, ld, k, 0.25);
+            L.h *= 0.25;
+            L.neq = 0;
+            return SR_RETRY;
+        }
+    }
+    const double tol = fmax(10.0 * EPS / rtol, fmin(0.03, sqrt(rtol)));
+    double d[N], yn[N];
+#pragma unroll
+    for (int i = 0; i < N; i++) {
+        d[i] = 0.0;
+        yn[i] = yp[i];
+    }
+    bool conv = false;
+    double dn_old = -1.0;
+    for (int it = 0; it < 4; it++) {
+        double f[N];
+        rhs(P, L.rho, yn, f);
+        L.n_rhs++;
+        bool fin = true;
+#pragma unroll
+        for (int i = 0; i < N; i++) {
+            f[i] = c * f[i] - psi[i] - d[i];
+            fin = fin && isfinite(f[i]);
+        }
+        if (!fin) break;
+        lu_solve<N>(A, L.piv, f);
+        L.n_solve++;
+        const double dn = wrms<N>(f, isc);
+        const double rate = dn_old > 0.0 ? dn / dn_old : -1.0;
+        if (rate >= 0.0) {
+            double rp = 1.0;
+            for (int q = 0; q < 4 - it; q++) rp *= rate;
+            if (rate >= 1.0 || rp / (1.0 - rate) * dn > tol) break;
+        }
+#pragma unroll
+        for (int i = 0; i < N; i++) {
+            yn[i] += f[i];
+            d[i] += f[i];
+        }
+        if (dn == 0.0 || (rate >= 0.0 && rate / (1.0 - rate) * dn < tol)) {
+            conv = true;
+            break;
+        }
+        dn_old = dn;
+    }
+    if (!conv) {
+        if (!L.jac_fresh) {       // refresh J and LU, same step size
+            L.lu_ok = false;
+            return SR_RETRY;
+        }
+        rescale<N>(D, ld, k, 0.5);
+        L.h *= 0.5;
+        L.neq = 0;
+        return SR_RETRY;
+    }
+    // error test
+    double ise[N], e1[N];
+#pragma unroll
+    for (int i = 0; i < N; i++) {
+        ise[i] = 1.0 / (atol + rtol * fabs(yn[i]));
+        e1[i] = d[i] * (1.0 / (k + 1));
+    }
+    const double en = wrms<N>(e1, ise);
+    if (en > 1.0) {
+        const double fac = fmax(0.2, 0.9 * pow(en, -1.0 / (k + 1)));
+        rescale<N>(D, ld, k, fac);
+        L.h *= fac;
+        L.neq = 0;
+        return SR_RETRY;
+    }
+    // accept: D_{k+2} = d - D_{k+1}, D_{k+1} = d, D_j += D_{j+1} for j = k..0
+    L.n_steps++;
+    L.t = tn;
+    L.jac_fresh = false;
+#pragma unroll
+    for (int i = 0; i < N; i++) {
+        double dv[MAXORD + 3];
+#pragma unroll
+        for (int j = 0; j <= MAXORD + 1; j++) dv[j] = (j <= k + 1) ? D[(j * N + i) * ld] : 0.0;
+        D[((k + 2) * N + i) * ld] = d[i] - D[((k + 1) * N + i) * ld];
+        double acc = d[i];
+        D[((k + 1) * N + i) * ld] = acc;
+#pragma unroll
+        for (int j = MAXORD; j >= 0; j--) {
+            if (j <= k) {
+                acc = dv[j] + acc;
+                D[(j * N + i) * ld] = acc;
+            }
+        }
+    }
+    L.neq++;
+    if (last) return SR_DONE;
+    if (L.neq < k + 1) return SR_ACCEPT;
+    // order and step-size selection
+    double em = 0.0, ep = 0.0;
+    {
+        double v[N];
+        if (k > 1) {
+#pragma unroll
+            for (int i = 0; i < N; i++) v[i] = D[(k * N + i) * ld] * (1.0 / k);
+            em = wrms<N>(v, ise);
+        }
+        if (k < MAXORD) {
+#pragma unroll
+            for (int i = 0; i < N; i++) v[i] = D[((k + 2) * N + i) * ld] * (1.0 / (k + 2));
+            ep = wrms<N>(v, ise);
+        }
+    }
+    const double f0 = pow(en, -1.0 / (k + 1));
+    const double fm = (k > 1) ? pow(em, -1.0 / k) : 0.0;
+    const double fp = (k < MAXORD) ? pow(ep, -1.0 / (k + 2)) : 0.0;
+    int dk = 0;
+    double best = f0;
+    if (fm > best) {
+        best = fm;
+        dk = -1;
+    }
+    if (fp > best) {
+        best = fp;
+        dk = 1;
+    }
+    L.k = k + dk;
+    const double fac = fmin(10.0, 0.9 * best);
+    rescale<N>(D, ld, L.k, fac);
+    L.h *= fac;
+    L.neq = 0;
+    return SR_ACCEPT;
+}
+
+// Initial state of a fresh cell: D_0 = y0, D_1 = h f(y0), order 1, with the
+// starting step of Hairer, Norsett & Wanner (Solving ODEs I, Sec. II.4).
+template <class M>
+__device__ void bdf_init(const Params<M>& P, Lane<M>& L, double* D, int64_t ld, const double* y0,
+                         double rtol, double atol) {
+    constexpr int N = M::N;
+    double f0[N], isc[N], y1[N], f1[N];
+    rhs(P, L.rho, y0, f0);
+#pragma unroll
+    for (int i = 0; i < N; i++) isc[i] = 1.0 / (atol + rtol * fabs(y0[i]));
+    const double d0 = wrms<N>(y0, isc), d1 = wrms<N>(f0, isc);
+    double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
+    h0 = fmin(h0, L.tend);
+#pragma unroll
+    for (int i = 0; i < N; i++) y1[i] = y0[i] + h0 * f0[i];
+    rhs(P, L.rho, y1, f1);
+    L.n_rhs += 2;
+#pragma unroll
+    for (int i = 0; i < N; i++) f1[i] -= f0[i];
+    const double d2 = wrms<N>(f1, isc) / h0;
+    const double mx = fmax(d1, d2);
+    const double h1 = (mx <= 1e-15) ? fmax(1e-6, h0 * 1e-3) : sqrt(0.01 / mx);
+    L.h = fmin(fmin(100.0 * h0, h1), L.tend);
+#pragma unroll
+    for (int i = 0; i < N; i++) {
+        D[i * ld] = y0[i];
+        D[(N + i) * ld] = L.h * f0[i];
+    }
+    L.t = 0.0;
+    L.k = 1;
+    L.neq = 0;
+    L.att = 0;
+    L.lu_ok = false;
+    L.jac_fresh = false;
+    L.c_lu = 0.0;
+}
+
+// ------------------------------------------------------- integration kernel
+struct SaveArea {             // per active slot, lane-major [field][slot]
+    double* D;                // ND * N rows
+    double* LU;               // N * N rows
+    double* scal;             // 4 rows: t, h, c_lu, (unused)
+    int* ints;                // 4 rows: k, neq, att, flags(lu_ok | jac_fresh<<1)
+    int8_t* piv;              // N rows
+    int64_t ld;               // capacity (slots)
+};
+
+struct IntArgs {
+    const DevBox* boxes;
+    int nbox;
+    uint8_t* st_int;
+    const int* active_ids;    // slot -> global cell (BULK, SPARSE)
+    const int* items;         // SPARSE: item -> slot
+    const int* n_items_dev;   // BULK: n_active, SPARSE: n_sparse
+    int64_t n_items_host;     // PLAIN: total cells
+    int* queue;               // refill counter of this launch
+    int* unfinished;          // BULK: cells left unfinished by this round
+    int* rounds;              // BULK: number of rounds that passed the gate
+    const int* gate;          // BULK round > 0: previous round's unfinished count
+    int nstar;
+    uint8_t* flag;            // per slot: 0 fresh, 1 saved, 2 done
+    SaveArea sv;
+    double* laneD;            // ND * N rows x ldL
+    int64_t ldL;
+    int kmax;
+    double rtol, atol;
+    Counters* ctr;
+};
+
+template <class M, int MODE>
+__global__ void __launch_bounds__(64) k_integrate(const Params<M>* __restrict__ Pp, IntArgs a) {
+    constexpr int N = M::N, NS = M::NS;
+    __shared__ double lds[N * N * 64];
+    const Params<M>& P = *Pp;
+    const int lane = threadIdx.x;
+    double* A = lds + lane;
+    if (MODE == BULK) {
+        const int nact = *a.n_items_dev;
+        if (nact == 0) return;
+        if (a.gate && *a.gate <= a.nstar) return;
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(a.rounds, 1);
+    }
+    const int64_t n_items = (MODE == PLAIN) ? a.n_items_host : (int64_t)*a.n_items_dev;
+    const int64_t lslot = blockIdx.x * 64ll + lane;
+    double* D = a.laneD + lslot;
+    const int64_t ld = a.ldL;
+
+    Lane<M> L;
+    L.n_steps = L.n_att = L.n_rhs = L.n_jac = L.n_lu = L.n_solve = 0;
+    unsigned long long max_att = 0, incomplete = 0, unfinished = 0;
+    int64_t cur = -1;     // current item
+    int slot = -1;
+    int64_t g = -1;
+    int bidx = 0;
+    bool exhausted = false;
+    bool static_taken = false;
+
+    for (;;) {
+        // ---- pick up work
+        if (MODE == PLAIN) {
+            if (cur < 0 && !static_taken) {
+                static_taken = true;
+                const int64_t it = lslot;
+                if (it < n_items && a.st_int[it] == ST_ACTIVE) cur = it;
+            }
+        } else {
+            for (;;) {
+                const bool need = cur < 0 && !exhausted;
+                const unsigned long long m = wave_ballot(need);
+                if (!m) break;
+                const int cnt = __popcll(m);
+                const int leader = __ffsll((long long)m) - 1;
+                int base = 0;
+                if (lane == leader) base = atomicAdd(a.queue, cnt);
+                base = __shfl(base, leader);
+                if (need) {
+                    const int my = base + __popcll(m & ((1ull << lane) - 1ull));
+                    if (my < n_items) {
+                        const int s = (MODE == SPARSE) ? a.items[my] : my;
+                        if (a.flag[s] != 2) {
+                            cur = my;
+                            slot = s;
+                        }
+                    } else {
+                        exhausted = true;
+                    }
+                }
+            }
+        }
+        if (wave_ballot(cur >= 0) == 0) break;
+        if (cur < 0) continue;
+        // ---- a cell was just taken: load it
+        if (g < 0) {
+            g = (MODE == PLAIN) ? cur : (int64_t)a.active_ids[slot];
+            bidx = find_box(a.boxes, a.nbox, g);
+            const DevBox& B = a.boxes[bidx];
+            const int64_t i = g - B.off;
+            L.rho = B.rho[i];
+            L.tend = B.dt;
+            L.round_att = 0;
+            if (MODE != PLAIN && a.flag[slot] == 1) {
+                const SaveArea& S = a.sv;
+#pragma unroll
+                for (int r = 0; r < ND * N; r++) D[r * ld] = S.D[r * S.ld + slot];
+#pragma unroll
+                for (int r = 0; r < N * N; r++) A[r * 64] = S.LU[r * S.ld + slot];
+#pragma unroll
+                for (int r = 0; r < N; r++) L.piv[r] = S.piv[r * S.ld + slot];
+                L.t = S.scal[0 * S.ld + slot];
+                L.h = S.scal[1 * S.ld + slot];
+                L.c_lu = S.scal[2 * S.ld + slot];
+                L.k = S.ints[0 * S.ld + slot];
+                L.neq = S.ints[1 * S.ld + slot];
+                L.att = S.ints[2 * S.ld + slot];
+                const int fl = S.ints[3 * S.ld + slot];
+                L.lu_ok = fl & 1;
+                L.jac_fresh = (fl >> 1) & 1;
+            } else {
+                double y0[N];
+#pragma unroll
+                for (int k = 0; k < NS; k++) y0[k] = B.Y[k * B.ldY + i];
+                y0[NS] = B.T[i];
+                bdf_init(P, L, D, ld, y0, a.rtol, a.atol);
+            }
+        }
+        // ---- one step attempt
+        const int r = bdf_attempt(P, L, D, ld, A, a.rtol, a.atol);
+        bool finished = false, save = false;
+        uint8_t st = ST_DONE;
+        if (r == SR_DONE) {
+            finished = true;
+        } else if (r == SR_FAIL) {
+            finished = true;
+            st = ST_FAIL;
+        } else if (L.round_att >= a.kmax) {
+            if (MODE == BULK) save = true;
+            else {
+                finished = true;
+                st = ST_KMAX;
+            }
+        }
+        if (finished || save) {
+            max_att = max(max_att, (unsigned long long)L.att);
+            if (finished) {
+                const DevBox& B = a.boxes[bidx];
+                const int64_t i = g - B.off;
+#pragma unroll
+                for (int k = 0; k < NS; k++) B.Y[k * B.ldY + i] = D[k * ld];
+                B.T[i] = D[NS * ld];
+                a.st_int[g] = st;
+                if (B.status) B.status[i] = st;
+                if (MODE != PLAIN) a.flag[slot] = 2;
+                if (st != ST_DONE) incomplete++;
+            } else {
+                const SaveArea& S = a.sv;
+#pragma unroll
+                for (int rr = 0; rr < ND * N; rr++) S.D[rr * S.ld + slot] = D[rr * ld];
+#pragma unroll
+                for (int rr = 0; rr < N * N; rr++) S.LU[rr * S.ld + slot] = A[rr * 64];
+#pragma unroll
+                for (int rr = 0; rr < N; rr++) S.piv[rr * S.ld + slot] = (int8_t)L.piv[rr];
+                S.scal[0 * S.ld + slot] = L.t;
+                S.scal[1 * S.ld + slot] = L.h;
+                S.scal[2 * S.ld + slot] = L.c_lu;
+                S.ints[0 * S.ld + slot] = L.k;
+                S.ints[1 * S.ld + slot] = L.neq;
+                S.ints[2 * S.ld + slot] = L.att;
+                S.ints[3 * S.ld + slot] = (L.lu_ok ? 1 : 0) | (L.jac_fresh ? 2 : 0);
+                a.flag[slot] = 1;
+                unfinished++;
+            }
+            cur = -1;
+            g = -1;
+            slot = -1;
+        }
+    }
+    // ---- statistics: one atomic per wave and counter
+    auto wsum = [&](unsigned long long v) {
+        for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+        return v;
+    };
+    auto wmax = [&](unsigned long long v) {
+        for (int o = 32; o >= 1; o >>= 1) v = max(v, (unsigned long long)__shfl_xor(v, o));
+        return v;
+    };
+    const unsigned long long s0 = wsum(L.n_steps), s1 = wsum(L.n_att), s2 = wsum(L.n_rhs),
+                             s3 = wsum(L.n_jac), s4 = wsum(L.n_lu), s5 = wsum(L.n_solve),
+                             s6 = wmax(max_att), s7 = wsum(incomplete), s8 = wsum(unfinished);
+    if (lane == 0) {
+        atomicAdd(&a.ctr->steps, s0);
+        atomicAdd(&a.ctr->attempts, s1);
+        atomicAdd(&a.ctr->rhs, s2);
+        atomicAdd(&a.ctr->jac, s3);
+        atomicAdd(&a.ctr->lu, s4);
+        atomicAdd(&a.ctr->solves, s5);
+        atomicMax(&a.ctr->max_attempts, s6);
+        atomicAdd(&a.ctr->incomplete, s7);
+        if (MODE == BULK && s8) atomicAdd(a.unfinished, (int)s8);
+    }
+}
+
+}  // namespace chem

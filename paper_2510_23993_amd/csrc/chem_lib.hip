@@ -1,0 +1,598 @@
+// libchem: C ABI (include/chem.h) over the HIP kernels of the stiff
+// chemistry hot path.  Host logic: mechanism loading and kernel selection,
+// per-context workspace, the enqueued plain / bulk-sparse pipelines, box
+// tables with hipGraph capture and replay, statistics.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "chem.h"
+#include "chem_host_mech.hpp"
+#include "chem_kernels.hpp"
+#include "gen/mech_list.hpp"
+
+using namespace chem;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(x)                                                                         \
+    do {                                                                                  \
+        hipError_t e_ = (x);                                                              \
+        if (e_ != hipSuccess) return fail(CHEM_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int RMAX = 64;  // most bulk-round launches per pipeline
+// device int counters
+enum { I_NACT = 0, I_NSP = 1, I_ROUNDS = 2, I_Q = 4, I_UNF = I_Q + RMAX + 2, I_COUNT = I_UNF + RMAX };
+
+struct Options {
+    int algorithm = 1;
+    double t_react_min = 500.0;
+    int kmax_bulk = 5;
+    int nactive_star = 10000;
+    int kmax_sparse = 100000;
+    int max_rounds = 24;
+    int grid_waves = 0;
+    int precision = 0;
+    int use_graph = 1;
+    bool operator==(const Options& o) const { return !memcmp(this, &o, sizeof(Options)); }
+};
+
+struct Buf {
+    void* p = nullptr;
+    size_t n = 0;
+    int grow(size_t bytes) {
+        if (bytes <= n) return 0;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            p = nullptr;
+            return -1;
+        }
+        n = bytes;
+        return 0;
+    }
+    ~Buf() {
+        if (p) (void)hipFree(p);
+    }
+    template <class T>
+    T* as() const {
+        return (T*)p;
+    }
+};
+
+}  // namespace
+
+struct chem_mech_s;
+
+// Kernel family instantiated for one compiled mechanism structure.
+struct MechOps {
+    uint64_t hash;
+    int ns, nr;
+    const char* tag;
+    int (*upload)(const HostMech&, void** dparams);
+    int (*pipeline)(struct chem_ctx_s*, int64_t total, int nbox, double rtol, double atol);
+    int (*prepare)(struct chem_ctx_s*, int64_t, const double*, const double*, const double*, int64_t, double*, double*);
+    int (*eval)(struct chem_ctx_s*, int64_t, const double*, const double*, double*, double*);
+    int (*lds_blocks)(int device);
+};
+
+struct chem_mech_s {
+    HostMech hm;
+    const MechOps* ops = nullptr;
+    void* dparams = nullptr;
+    int device = 0;
+};
+
+struct chem_ctx_s {
+    chem_mech_s* m = nullptr;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    Options opt;
+    int ncu = 0;
+    // workspace
+    Buf st_int, active, sparse, flag, bcnt, boff, ints, ctr, save, laneD, boxes;
+    int64_t cap_cells = 0, cap_lanes = 0;
+    DevBox* h_boxes = nullptr;  // pinned staging of the box table
+    size_t h_boxes_cap = 0;
+    hipEvent_t ev_copy = nullptr, ev0 = nullptr, ev1 = nullptr;
+    // graph cache for chem_integrate_boxes
+    hipGraphExec_t gexec = nullptr;
+    std::vector<chem_box> gkey;
+    double g_rtol = 0, g_atol = 0;
+    Options g_opt;
+};
+
+namespace {
+
+template <class M>
+int upload_params(const HostMech& h, void** out) {
+    if (h.ns != M::NS || (int)h.rx.size() != M::NR) return fail(CHEM_E_MECH, "size mismatch");
+    auto P = std::make_unique<Params<M>>();
+    memset(P.get(), 0, sizeof(Params<M>));
+    for (int k = 0; k < M::NS; k++) {
+        P->W[k] = h.W[k];
+        P->invW[k] = 1.0 / h.W[k];
+        P->Tmid[k] = h.Tmid[k];
+        const double* lo = &h.alo[7 * k];
+        const double* hi = &h.ahi[7 * k];
+        const double* src[2] = {lo, hi};
+        double(*H[2])[6] = {P->hlo, P->hhi};
+        double(*S[2])[6] = {P->slo, P->shi};
+        double(*Cc[2])[5] = {P->clo, P->chi};
+        for (int r = 0; r < 2; r++) {
+            const double* a = src[r];
+            const double hc[6] = {a[0], a[1] / 2, a[2] / 3, a[3] / 4, a[4] / 5, a[5]};
+            const double sc[6] = {a[0], a[1], a[2] / 2, a[3] / 3, a[4] / 4, a[6]};
+            for (int q = 0; q < 6; q++) {
+                H[r][k][q] = hc[q];
+                S[r][k][q] = sc[q];
+            }
+            for (int q = 0; q < 5; q++) Cc[r][k][q] = a[q];
+        }
+    }
+    for (int j = 0; j < M::NR; j++) {
+        const HostReaction& r = h.rx[j];
+        P->lnA[j] = std::log(r.A);
+        P->b[j] = r.b;
+        P->EaR[j] = r.Ea / RGAS;
+        P->lnA0[j] = r.type == 2 ? std::log(r.A0) : 0.0;
+        P->b0[j] = r.b0;
+        P->Ea0R[j] = r.Ea0 / RGAS;
+        for (int q = 0; q < 4; q++) P->troe[j][q] = r.troe[q];
+        for (int k = 0; k < M::NS; k++) P->eff[j][k] = r.eff[k];
+    }
+    void* d = nullptr;
+    HIPCHK(hipMalloc(&d, sizeof(Params<M>)));
+    HIPCHK(hipMemcpy(d, P.get(), sizeof(Params<M>), hipMemcpyHostToDevice));
+    *out = d;
+    return 0;
+}
+
+template <class M>
+int lds_blocks_per_cu(int device) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_integrate<M, SPARSE>, 64, 0) != hipSuccess || nb <= 0)
+        nb = 1;
+    (void)device;
+    return nb;
+}
+
+int ensure_ws(chem_ctx_s* c, int64_t cells, int64_t lanes, int N) {
+    const int64_t nb = (cells + 255) / 256 + 1;
+    if (c->st_int.grow(cells) || c->active.grow(cells * 4) || c->sparse.grow(cells * 4) ||
+        c->flag.grow(cells) || c->bcnt.grow(nb * 4) || c->boff.grow(nb * 4) ||
+        c->ints.grow(I_COUNT * 4) || c->ctr.grow(sizeof(Counters)))
+        return fail(CHEM_E_NOMEM, "workspace allocation failed");
+    const size_t per_slot = sizeof(double) * (ND * N + N * N + 4) + sizeof(int) * 4 + N;
+    if (cells > c->cap_cells) {
+        if (c->save.grow(per_slot * (size_t)cells)) return fail(CHEM_E_NOMEM, "save-area allocation failed");
+        c->cap_cells = cells;
+    }
+    if (lanes > c->cap_lanes) {
+        if (c->laneD.grow(sizeof(double) * ND * N * (size_t)lanes)) return fail(CHEM_E_NOMEM, "lane workspace allocation failed");
+        c->cap_lanes = lanes;
+    }
+    return 0;
+}
+
+SaveArea save_area(chem_ctx_s* c, int N) {
+    SaveArea s;
+    const int64_t L = c->cap_cells;
+    char* p = c->save.as<char>();
+    s.ld = L;
+    s.D = (double*)p;
+    p += sizeof(double) * ND * N * L;
+    s.LU = (double*)p;
+    p += sizeof(double) * N * N * L;
+    s.scal = (double*)p;
+    p += sizeof(double) * 4 * L;
+    s.ints = (int*)p;
+    p += sizeof(int) * 4 * L;
+    s.piv = (int8_t*)p;
+    return s;
+}
+
+int64_t persistent_grid(chem_ctx_s* c) {
+    const int per_cu = c->opt.grid_waves > 0 ? c->opt.grid_waves : c->m->ops->lds_blocks(c->device);
+    return (int64_t)per_cu * c->ncu;
+}
+
+int64_t lanes_needed(chem_ctx_s* c, int64_t total) {
+    return std::max<int64_t>(persistent_grid(c) * 64, c->opt.algorithm == 0 ? ((total + 63) / 64) * 64 : 0);
+}
+
+template <class M>
+int pipeline(chem_ctx_s* c, int64_t total, int nbox, double rtol, double atol) {
+    constexpr int N = M::N;
+    const Options& o = c->opt;
+    hipStream_t s = c->stream;
+    const int64_t grid = persistent_grid(c);
+    int rc = ensure_ws(c, std::max<int64_t>(total, 1), lanes_needed(c, total), N);
+    if (rc) return rc;
+    const Params<M>* P = (const Params<M>*)c->m->dparams;
+    const DevBox* db = c->boxes.as<DevBox>();
+    int* I = c->ints.as<int>();
+    Counters* ctr = c->ctr.as<Counters>();
+    const int64_t nb = std::max<int64_t>(1, (total + 255) / 256);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, s, I, (int64_t)I_COUNT, 0);
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, (unsigned long long*)ctr,
+                       (int64_t)(sizeof(Counters) / 8));
+    const double tmin = o.algorithm == 1 ? o.t_react_min : -1.0;
+    hipLaunchKernelGGL((k_screen<M>), dim3(nb), dim3(256), 0, s, P, db, nbox, total, tmin,
+                       c->st_int.as<uint8_t>(), c->bcnt.as<int>());
+    IntArgs a{};
+    a.boxes = db;
+    a.nbox = nbox;
+    a.st_int = c->st_int.as<uint8_t>();
+    a.active_ids = c->active.as<int>();
+    a.flag = c->flag.as<uint8_t>();
+    a.sv = save_area(c, N);
+    a.laneD = c->laneD.as<double>();
+    a.ldL = c->cap_lanes;
+    a.rtol = rtol;
+    a.atol = atol;
+    a.ctr = ctr;
+    a.nstar = o.nactive_star;
+    a.rounds = I + I_ROUNDS;
+    if (o.algorithm == 0) {
+        a.n_items_host = total;
+        a.kmax = o.kmax_sparse;
+        hipLaunchKernelGGL((k_integrate<M, PLAIN>), dim3((total + 63) / 64), dim3(64), 0, s, P, a);
+        return 0;
+    }
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, c->bcnt.as<int>(), (int)nb, c->boff.as<int>(), I + I_NACT);
+    hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(256), 0, s, c->st_int.as<uint8_t>(), total, c->boff.as<int>(),
+                       c->active.as<int>());
+    hipLaunchKernelGGL(k_fill_u8, dim3(std::min<int64_t>(nb, 4096)), dim3(256), 0, s, c->flag.as<uint8_t>(),
+                       std::max<int64_t>(total, 1), (uint8_t)0);
+    const int rounds = std::min(o.max_rounds, RMAX);
+    for (int r = 0; r < rounds; r++) {
+        IntArgs b = a;
+        b.n_items_dev = I + I_NACT;
+        b.queue = I + I_Q + r;
+        b.unfinished = I + I_UNF + r;
+        b.gate = r == 0 ? I + I_NACT : I + I_UNF + r - 1;
+        b.kmax = o.kmax_bulk;
+        hipLaunchKernelGGL((k_integrate<M, BULK>), dim3(grid), dim3(64), 0, s, P, b);
+    }
+    hipLaunchKernelGGL(k_count_unfinished, dim3(nb), dim3(256), 0, s, c->flag.as<uint8_t>(), I + I_NACT,
+                       c->bcnt.as<int>());
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, c->bcnt.as<int>(), (int)nb, c->boff.as<int>(), I + I_NSP);
+    hipLaunchKernelGGL(k_scatter_unfinished, dim3(nb), dim3(256), 0, s, c->flag.as<uint8_t>(), I + I_NACT,
+                       c->boff.as<int>(), c->sparse.as<int>());
+    IntArgs sp = a;
+    sp.items = c->sparse.as<int>();
+    sp.n_items_dev = I + I_NSP;
+    sp.queue = I + I_Q + RMAX;
+    sp.kmax = o.kmax_sparse;
+    hipLaunchKernelGGL((k_integrate<M, SPARSE>), dim3(grid), dim3(64), 0, s, P, sp);
+    return 0;
+}
+
+template <class M>
+int prepare(chem_ctx_s* c, int64_t n, const double* T, const double* p, const double* Y, int64_t ldY,
+            double* rho, double* e) {
+    if (n == 0) return 0;
+    hipLaunchKernelGGL((k_prepare<M>), dim3((n + 255) / 256), dim3(256), 0, c->stream,
+                       (const Params<M>*)c->m->dparams, n, T, p, Y, ldY, rho, e);
+    HIPCHK(hipGetLastError());
+    return 0;
+}
+
+template <class M>
+int eval(chem_ctx_s* c, int64_t n, const double* rho, const double* y, double* f, double* J) {
+    if (n == 0) return 0;
+    hipLaunchKernelGGL((k_eval_rhs<M>), dim3((n + 63) / 64), dim3(64), 0, c->stream,
+                       (const Params<M>*)c->m->dparams, n, rho, y, f, J);
+    HIPCHK(hipGetLastError());
+    return 0;
+}
+
+#define CHEM_OPS(M) {M::HASH, M::NS, M::NR, M::TAG, upload_params<M>, pipeline<M>, prepare<M>, eval<M>, lds_blocks_per_cu<M>},
+const MechOps g_ops[] = {CHEM_FOR_EACH_MECH(CHEM_OPS)};
+
+int stage_boxes(chem_ctx_s* c, const std::vector<DevBox>& v) {
+    const size_t bytes = v.size() * sizeof(DevBox);
+    if (c->boxes.grow(bytes)) return fail(CHEM_E_NOMEM, "box table allocation failed");
+    if (bytes > c->h_boxes_cap) {
+        if (c->h_boxes) {
+            HIPCHK(hipEventSynchronize(c->ev_copy));
+            HIPCHK(hipHostFree(c->h_boxes));
+        }
+        c->h_boxes = nullptr;
+        HIPCHK(hipHostMalloc((void**)&c->h_boxes, bytes));
+        c->h_boxes_cap = bytes;
+    } else {
+        HIPCHK(hipEventSynchronize(c->ev_copy));  // previous upload finished reading the staging buffer
+    }
+    memcpy(c->h_boxes, v.data(), bytes);
+    HIPCHK(hipMemcpyAsync(c->boxes.p, c->h_boxes, bytes, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipEventRecord(c->ev_copy, c->stream));
+    return 0;
+}
+
+int finish_stats(chem_ctx_s* c, int64_t total, chem_stats* st) {
+    HIPCHK(hipEventRecord(c->ev1, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    int I[I_COUNT];
+    Counters ct;
+    HIPCHK(hipMemcpy(I, c->ints.p, sizeof(I), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(&ct, c->ctr.p, sizeof(ct), hipMemcpyDeviceToHost));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    memset(st, 0, sizeof(*st));
+    st->ncell = total;
+    st->n_active0 = c->opt.algorithm == 1 ? I[I_NACT] : -1;
+    st->n_active_after_bulk = c->opt.algorithm == 1 ? I[I_NSP] : -1;
+    st->n_sparse = c->opt.algorithm == 1 ? I[I_NSP] : 0;
+    st->n_bulk_rounds = I[I_ROUNDS];
+    st->n_incomplete = (int64_t)ct.incomplete;
+    st->steps_total = (int64_t)ct.steps;
+    st->attempts_total = (int64_t)ct.attempts;
+    st->rhs_evals = (int64_t)ct.rhs;
+    st->jac_evals = (int64_t)ct.jac;
+    st->lu_facts = (int64_t)ct.lu;
+    st->lin_solves = (int64_t)ct.solves;
+    st->max_steps_cell = (int64_t)ct.max_attempts;
+    st->t_total_ms = ms;
+    return ct.incomplete ? CHEM_W_INCOMPLETE : CHEM_OK;
+}
+
+int check_box(const chem_box& b, int nspec) {
+    (void)nspec;
+    if (b.ncell < 0) return fail(CHEM_E_INVAL, "ncell < 0");
+    if (b.ncell == 0) return 0;
+    if (!b.rho || !b.e || !b.Y || !b.T) return fail(CHEM_E_INVAL, "NULL state pointer");
+    if (b.ldY < b.ncell) return fail(CHEM_E_INVAL, "ldY < ncell");
+    if (!(b.dt > 0) || !std::isfinite(b.dt)) return fail(CHEM_E_INVAL, "dt must be positive and finite");
+    return 0;
+}
+
+int run(chem_ctx_s* c, const std::vector<chem_box>& bx, double rtol, double atol, chem_stats* st,
+        bool allow_graph) {
+    if (!(rtol > 0) || !(atol >= 0) || !std::isfinite(rtol) || !std::isfinite(atol))
+        return fail(CHEM_E_INVAL, "rtol must be > 0 and atol >= 0");
+    std::vector<DevBox> v;
+    int64_t off = 0;
+    for (const auto& b : bx) {
+        int rc = check_box(b, c->m->hm.ns);
+        if (rc) return rc;
+        if (b.ncell == 0) continue;
+        DevBox d{b.rho, b.e, b.Y, b.T, b.mask, b.status, b.ncell, b.ldY, off, b.dt};
+        v.push_back(d);
+        off += b.ncell;
+    }
+    if (off > (int64_t)INT32_MAX - 1) return fail(CHEM_E_INVAL, "more than 2^31 - 2 cells in one call");
+    HIPCHK(hipSetDevice(c->device));
+    if (st) HIPCHK(hipEventRecord(c->ev0, c->stream));
+    if (off == 0) {   // nothing to do; no kernel is enqueued
+        if (st) {
+            memset(st, 0, sizeof(*st));
+            HIPCHK(hipStreamSynchronize(c->stream));
+        }
+        return 0;
+    }
+    const bool use_graph = allow_graph && c->opt.use_graph;
+    const bool hit = use_graph && c->gexec && c->gkey.size() == bx.size() && c->g_rtol == rtol &&
+                     c->g_atol == atol && c->g_opt == c->opt &&
+                     !memcmp(c->gkey.data(), bx.data(), bx.size() * sizeof(chem_box));
+    if (hit) {
+        HIPCHK(hipGraphLaunch(c->gexec, c->stream));
+    } else {
+        int rc = stage_boxes(c, v);
+        if (rc) return rc;
+        if (use_graph) {
+            // workspace must exist before capture: run the sizing once (no kernels)
+            rc = ensure_ws(c, off, lanes_needed(c, off), c->m->hm.ns + 1);
+            if (rc) return rc;
+            if (c->gexec) {
+                (void)hipGraphExecDestroy(c->gexec);
+                c->gexec = nullptr;
+            }
+            hipGraph_t graph = nullptr;
+            HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+            rc = c->m->ops->pipeline(c, off, (int)v.size(), rtol, atol);
+            hipError_t e1 = hipStreamEndCapture(c->stream, &graph);
+            if (rc) return rc;
+            if (e1 != hipSuccess) return fail(CHEM_E_HIP, std::string("graph capture: ") + hipGetErrorString(e1));
+            hipError_t e2 = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e2 != hipSuccess) return fail(CHEM_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(e2));
+            c->gkey = bx;
+            c->g_rtol = rtol;
+            c->g_atol = atol;
+            c->g_opt = c->opt;
+            HIPCHK(hipGraphLaunch(c->gexec, c->stream));
+        } else {
+            rc = c->m->ops->pipeline(c, off, (int)v.size(), rtol, atol);
+            if (rc) return rc;
+        }
+    }
+    HIPCHK(hipGetLastError());
+    if (st) return finish_stats(c, off, st);
+    return 0;
+}
+
+struct OptKey {
+    const char* name;
+    double lo, hi;
+};
+
+}  // namespace
+
+extern "C" {
+
+const char* chem_last_error(void) { return g_err.c_str(); }
+
+int chem_load_mechanism(const char* path, chem_mech_t* out) {
+    if (!path || !out) return fail(CHEM_E_INVAL, "NULL argument");
+    *out = nullptr;
+    HostMech h;
+    try {
+        h = parse_mechanism(path);
+    } catch (const std::exception& ex) {
+        return fail(CHEM_E_MECH, ex.what());
+    }
+    const MechOps* ops = nullptr;
+    for (const auto& o : g_ops)
+        if (o.hash == h.hash && o.ns == h.ns && o.nr == (int)h.rx.size()) ops = &o;
+    if (!ops) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "no kernels compiled for this mechanism structure (hash %016llx); "
+                 "add it to the build's mechanism list", (unsigned long long)h.hash);
+        return fail(CHEM_E_MECH, buf);
+    }
+    auto m = std::make_unique<chem_mech_s>();
+    m->hm = std::move(h);
+    m->ops = ops;
+    if (hipGetDevice(&m->device) != hipSuccess) return fail(CHEM_E_HIP, "hipGetDevice failed");
+    int rc = ops->upload(m->hm, &m->dparams);
+    if (rc) return rc;
+    *out = m.release();
+    return CHEM_OK;
+}
+
+int chem_mech_info(chem_mech_t m, int* nspec, int* nreac, const double** W) {
+    if (!m) return fail(CHEM_E_INVAL, "NULL mechanism");
+    if (nspec) *nspec = m->hm.ns;
+    if (nreac) *nreac = (int)m->hm.rx.size();
+    if (W) *W = m->hm.W.data();
+    return 0;
+}
+
+int chem_species_name(chem_mech_t m, int k, const char** name) {
+    if (!m || !name || k < 0 || k >= m->hm.ns) return fail(CHEM_E_INVAL, "bad species index");
+    *name = m->hm.species[k].c_str();
+    return 0;
+}
+
+void chem_free_mechanism(chem_mech_t m) {
+    if (!m) return;
+    if (m->dparams) (void)hipFree(m->dparams);
+    delete m;
+}
+
+int chem_ctx_create(chem_mech_t m, int device, void* stream, chem_ctx_t* out) {
+    if (!m || !out) return fail(CHEM_E_INVAL, "NULL argument");
+    *out = nullptr;
+    if (device != m->device) return fail(CHEM_E_INVAL, "context device differs from the mechanism's device");
+    HIPCHK(hipSetDevice(device));
+    auto c = std::make_unique<chem_ctx_s>();
+    c->m = m;
+    c->device = device;
+    c->stream = (hipStream_t)stream;
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, device));
+    c->ncu = prop.multiProcessorCount;
+    HIPCHK(hipEventCreateWithFlags(&c->ev_copy, hipEventDisableTiming));
+    HIPCHK(hipEventCreate(&c->ev0));
+    HIPCHK(hipEventCreate(&c->ev1));
+    HIPCHK(hipEventRecord(c->ev_copy, c->stream));
+    *out = c.release();
+    return CHEM_OK;
+}
+
+void chem_ctx_destroy(chem_ctx_t c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->h_boxes) (void)hipHostFree(c->h_boxes);
+    if (c->ev_copy) (void)hipEventDestroy(c->ev_copy);
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    delete c;
+}
+
+int chem_set_option(chem_ctx_t c, const char* key, double v) {
+    if (!c || !key) return fail(CHEM_E_INVAL, "NULL argument");
+    std::string k = key;
+    Options& o = c->opt;
+    auto in = [&](double lo, double hi) { return std::isfinite(v) && v >= lo && v <= hi; };
+    if (k == "algorithm" && in(0, 1)) o.algorithm = (int)v;
+    else if (k == "t_react_min" && in(0, 1e5)) o.t_react_min = v;
+    else if (k == "kmax_bulk" && in(1, 1e9)) o.kmax_bulk = (int)v;
+    else if (k == "nactive_star" && in(0, 2e9)) o.nactive_star = (int)v;
+    else if (k == "kmax_sparse" && in(1, 2e9)) o.kmax_sparse = (int)v;
+    else if (k == "max_rounds" && in(0, RMAX)) o.max_rounds = (int)v;
+    else if (k == "grid_waves" && in(0, 64)) o.grid_waves = (int)v;
+    else if (k == "precision" && in(0, 0)) o.precision = (int)v;
+    else if (k == "use_graph" && in(0, 1)) o.use_graph = (int)v;
+    else return fail(CHEM_E_INVAL, "unknown option or value out of range: " + k);
+    return CHEM_OK;
+}
+
+int chem_get_option(chem_ctx_t c, const char* key, double* v) {
+    if (!c || !key || !v) return fail(CHEM_E_INVAL, "NULL argument");
+    std::string k = key;
+    const Options& o = c->opt;
+    if (k == "algorithm") *v = o.algorithm;
+    else if (k == "t_react_min") *v = o.t_react_min;
+    else if (k == "kmax_bulk") *v = o.kmax_bulk;
+    else if (k == "nactive_star") *v = o.nactive_star;
+    else if (k == "kmax_sparse") *v = o.kmax_sparse;
+    else if (k == "max_rounds") *v = o.max_rounds;
+    else if (k == "grid_waves") *v = o.grid_waves;
+    else if (k == "precision") *v = o.precision;
+    else if (k == "use_graph") *v = o.use_graph;
+    else return fail(CHEM_E_INVAL, "unknown option: " + k);
+    return CHEM_OK;
+}
+
+int chem_integrate(chem_ctx_t c, int64_t ncell, const double* rho, const double* e, double* Y, int64_t ldY,
+                   double* T, const uint8_t* mask, uint8_t* status, double dt, double rtol, double atol,
+                   chem_stats* st) {
+    if (!c) return fail(CHEM_E_INVAL, "NULL context");
+    if (ncell < 0) return fail(CHEM_E_INVAL, "ncell < 0");
+    chem_box b{ncell, rho, e, Y, ldY, T, mask, status, dt, 0};
+    return run(c, {b}, rtol, atol, st, false);
+}
+
+int chem_integrate_boxes(chem_ctx_t c, int nbox, const chem_box* boxes, double rtol, double atol,
+                         chem_stats* st) {
+    if (!c || nbox < 0 || (nbox > 0 && !boxes)) return fail(CHEM_E_INVAL, "bad box table");
+    std::vector<chem_box> v(boxes, boxes + nbox);
+    return run(c, v, rtol, atol, st, true);
+}
+
+int chem_prepare_state(chem_ctx_t c, int64_t n, const double* T, const double* p, const double* Y,
+                       int64_t ldY, double* rho, double* e) {
+    if (!c || n < 0 || (n > 0 && (!T || !p || !Y || !rho || !e)) || ldY < n)
+        return fail(CHEM_E_INVAL, "bad arguments");
+    HIPCHK(hipSetDevice(c->device));
+    return c->m->ops->prepare(c, n, T, p, Y, ldY, rho, e);
+}
+
+int chem_eval_rhs(chem_ctx_t c, int64_t n, const double* rho, const double* y, double* f, double* J) {
+    if (!c || n < 0 || (n > 0 && (!rho || !y || !f))) return fail(CHEM_E_INVAL, "bad arguments");
+    HIPCHK(hipSetDevice(c->device));
+    return c->m->ops->eval(c, n, rho, y, f, J);
+}
+
+int chem_load_surrogate(chem_ctx_t c, const char* path) {
+    (void)c;
+    (void)path;
+    return fail(CHEM_E_STATE, "surrogate not available in this build");
+}
+
+int chem_synchronize(chem_ctx_t c) {
+    if (!c) return fail(CHEM_E_INVAL, "NULL context");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return CHEM_OK;
+}
+
+}  // extern "C"
