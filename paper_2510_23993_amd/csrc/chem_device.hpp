@@ -84,7 +84,7 @@ __device__ __forceinline__ void e_cv(const Params<M>& P, double T, const double*
 // Newton on e(T, Y) = e0 with a bisection guard in [100, 6000] K.
 // Returns false if e0 is outside [e(100), e(6000)].
 template <class M>
-__device__ bool T_from_e(const Params<M>& P, double e0, const double* Y, double Tg, double& Tout) {
+__device__ __forceinline__ bool T_from_e(const Params<M>& P, double e0, const double* Y, double Tg, double& Tout) {
     double lo = 100.0, hi = 6000.0, elo, ehi, cv;
     e_cv(P, lo, Y, elo, cv);
     e_cv(P, hi, Y, ehi, cv);
@@ -242,7 +242,7 @@ __device__ __forceinline__ void rhs_loop(const Params<M>& P, const CellEval<M>& 
 
 // f = dy/dt for y = (Y_1..Y_NS, T) at constant rho and e.
 template <class M>
-__device__ void rhs(const Params<M>& P, double rho, const double* y, double* f) {
+__device__ __forceinline__ void rhs(const Params<M>& P, double rho, const double* y, double* f) {
     CellEval<M> E;
     cell_eval(P, rho, y, E);
     double om[M::NS];
@@ -395,7 +395,7 @@ __device__ __forceinline__ void newton_matrix(const Params<M>& P, double rho, co
 // on, and solves replay the same sequence of interchanges.  Returns false
 // if a pivot is zero or not finite.
 template <int N>
-__device__ bool lu_factor(double* A, int* piv) {
+__device__ __forceinline__ bool lu_factor(double* A, int* piv) {
     bool ok = true;
 #pragma unroll
     for (int k = 0; k < N; k++) {

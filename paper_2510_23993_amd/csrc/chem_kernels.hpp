@@ -263,7 +263,7 @@ __device__ __forceinline__ double wrms(const double* v, const double* isc) {
 // D_j <- nabla'^j P(t_n) on the grid of spacing rho*h (j = 1..k; D_0 unchanged):
 // T_ji = sum_m (-1)^m C(j,m) b_i(m rho), b_i(x) = prod_{l=1..i} (l - 1 - x)/l.
 template <int N>
-__device__ void rescale(double* D, int64_t ld, int k, double r) {
+__device__ __forceinline__ void rescale(double* D, int64_t ld, int k, double r) {
     double Tm[MAXORD + 1][MAXORD + 1];
 #pragma unroll
     for (int j = 1; j <= MAXORD; j++) {
@@ -302,7 +302,7 @@ __device__ void rescale(double* D, int64_t ld, int k, double r) {
 enum StepResult { SR_RETRY = 0, SR_ACCEPT = 1, SR_DONE = 2, SR_FAIL = 3 };
 
 template <class M>
-__device__ int bdf_attempt(const Params<M>& P, Lane<M>& L, double* D, int64_t ld, double* A,
+__device__ __forceinline__ int bdf_attempt(const Params<M>& P, Lane<M>& L, double* D, int64_t ld, double* A,
                            double rtol, double atol) {
     constexpr int N = M::N;
     constexpr double EPS = 2.220446049250313e-16;
@@ -482,7 +482,7 @@ __device__ int bdf_attempt(const Params<M>& P, Lane<M>& L, double* D, int64_t ld
 // Initial state of a fresh cell: D_0 = y0, D_1 = h f(y0), order 1, with the
 // starting step of Hairer, Norsett & Wanner (Solving ODEs I, Sec. II.4).
 template <class M>
-__device__ void bdf_init(const Params<M>& P, Lane<M>& L, double* D, int64_t ld, const double* y0,
+__device__ __forceinline__ void bdf_init(const Params<M>& P, Lane<M>& L, double* D, int64_t ld, const double* y0,
                          double rtol, double atol) {
     constexpr int N = M::N;
     double f0[N], isc[N], y1[N], f1[N];

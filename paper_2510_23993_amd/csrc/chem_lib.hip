@@ -14,6 +14,7 @@
 
 #include "chem.h"
 #include "chem_host_mech.hpp"
+#include "chem_coop.hpp"
 #include "chem_kernels.hpp"
 #include "gen/mech_list.hpp"
 
@@ -48,6 +49,7 @@ struct Options {
     int grid_waves = 0;
     int precision = 0;
     int use_graph = 1;
+    int group = -1;   // lanes per cell: 0 = compiled one-lane kernel, 4..64 = cooperative, -1 = auto
     bool operator==(const Options& o) const { return !memcmp(this, &o, sizeof(Options)); }
 };
 
@@ -93,8 +95,10 @@ struct MechOps {
 
 struct chem_mech_s {
     HostMech hm;
-    const MechOps* ops = nullptr;
+    const MechOps* ops = nullptr;   // compiled one-lane kernels for this structure (may be null)
     void* dparams = nullptr;
+    CoopMech cm{};                  // data-driven device tables (every mechanism)
+    std::vector<void*> dbufs;
     int device = 0;
 };
 
@@ -172,23 +176,32 @@ int lds_blocks_per_cu(int device) {
     return nb;
 }
 
-int ensure_ws(chem_ctx_s* c, int64_t cells, int64_t lanes, int N) {
+// Workspace for one call.  The save area and the lane area are laid out with
+// stride = this call's cell / lane count, so their sizes are checked against
+// exactly that; any reallocation invalidates a captured graph (its nodes hold
+// the old addresses).
+int ensure_ws(chem_ctx_s* c, int64_t cells, int64_t lanes, size_t per_slot, size_t lane_bytes) {
     const int64_t nb = (cells + 255) / 256 + 1;
+    void* before[5] = {c->st_int.p, c->active.p, c->save.p, c->laneD.p, c->bcnt.p};
     if (c->st_int.grow(cells) || c->active.grow(cells * 4) || c->sparse.grow(cells * 4) ||
         c->flag.grow(cells) || c->bcnt.grow(nb * 4) || c->boff.grow(nb * 4) ||
         c->ints.grow(I_COUNT * 4) || c->ctr.grow(sizeof(Counters)))
         return fail(CHEM_E_NOMEM, "workspace allocation failed");
-    const size_t per_slot = sizeof(double) * (ND * N + N * N + 4) + sizeof(int) * 4 + N;
-    if (cells > c->cap_cells) {
-        if (c->save.grow(per_slot * (size_t)cells)) return fail(CHEM_E_NOMEM, "save-area allocation failed");
-        c->cap_cells = cells;
-    }
-    if (lanes > c->cap_lanes) {
-        if (c->laneD.grow(sizeof(double) * ND * N * (size_t)lanes)) return fail(CHEM_E_NOMEM, "lane workspace allocation failed");
-        c->cap_lanes = lanes;
+    if (c->save.grow(per_slot * (size_t)cells)) return fail(CHEM_E_NOMEM, "save-area allocation failed");
+    c->cap_cells = cells;
+    if (c->laneD.grow(std::max<size_t>(8, lane_bytes * (size_t)lanes)))
+        return fail(CHEM_E_NOMEM, "lane workspace allocation failed");
+    c->cap_lanes = lanes;
+    void* after[5] = {c->st_int.p, c->active.p, c->save.p, c->laneD.p, c->bcnt.p};
+    if (memcmp(before, after, sizeof before) && c->gexec) {
+        (void)hipGraphExecDestroy(c->gexec);
+        c->gexec = nullptr;
     }
     return 0;
 }
+
+size_t onelane_slot_bytes(int N) { return sizeof(double) * (ND * N + N * N + 4) + sizeof(int) * 4 + N; }
+size_t coop_slot_bytes(int NC) { return sizeof(double) * (ND * NC + NC * NC + 3) + sizeof(int) * (NC + 4); }
 
 SaveArea save_area(chem_ctx_s* c, int N) {
     SaveArea s;
@@ -208,7 +221,7 @@ SaveArea save_area(chem_ctx_s* c, int N) {
 }
 
 int64_t persistent_grid(chem_ctx_s* c) {
-    const int per_cu = c->opt.grid_waves > 0 ? c->opt.grid_waves : c->m->ops->lds_blocks(c->device);
+    const int per_cu = c->opt.grid_waves > 0 ? c->opt.grid_waves : (c->m->ops ? c->m->ops->lds_blocks(c->device) : 1);
     return (int64_t)per_cu * c->ncu;
 }
 
@@ -222,7 +235,8 @@ int pipeline(chem_ctx_s* c, int64_t total, int nbox, double rtol, double atol) {
     const Options& o = c->opt;
     hipStream_t s = c->stream;
     const int64_t grid = persistent_grid(c);
-    int rc = ensure_ws(c, std::max<int64_t>(total, 1), lanes_needed(c, total), N);
+    int rc = ensure_ws(c, std::max<int64_t>(total, 1), lanes_needed(c, total), onelane_slot_bytes(N),
+                       sizeof(double) * ND * N);
     if (rc) return rc;
     const Params<M>* P = (const Params<M>*)c->m->dparams;
     const DevBox* db = c->boxes.as<DevBox>();
@@ -299,6 +313,335 @@ int eval(chem_ctx_s* c, int64_t n, const double* rho, const double* y, double* f
     if (n == 0) return 0;
     hipLaunchKernelGGL((k_eval_rhs<M>), dim3((n + 63) / 64), dim3(64), 0, c->stream,
                        (const Params<M>*)c->m->dparams, n, rho, y, f, J);
+    HIPCHK(hipGetLastError());
+    return 0;
+}
+
+
+// ------------------------------------------------------- data-driven tables
+int upload_coop_tables(chem_mech_s* m) {
+    const HostMech& h = m->hm;
+    const int ns = h.ns, nr = (int)h.rx.size();
+    for (const auto& r : h.rx)
+        if ((int)r.re.size() > CMP || (int)r.pr.size() > CMP)
+            return fail(CHEM_E_MECH, "a reaction has more than 4 participants on one side");
+    // reorder reactions: falloff, third-body, elementary (less divergence per slot)
+    std::vector<int> order;
+    for (int t : {2, 1, 0})
+        for (int j = 0; j < nr; j++)
+            if (h.rx[j].type == t) order.push_back(j);
+    std::vector<double> sp((size_t)ns * SPS, 0.0), rx((size_t)std::max(nr, 1) * RXS, 0.0), effa;
+    std::vector<int> rxi((size_t)std::max(nr, 1) * RXI, 0), effs, ptr(ns + 1, 0), crx;
+    std::vector<double> cnu;
+    for (int k = 0; k < ns; k++) {
+        double* q = &sp[(size_t)k * SPS];
+        q[SP_W] = h.W[k];
+        q[SP_INVW] = 1.0 / h.W[k];
+        q[SP_TMID] = h.Tmid[k];
+        const double* set[2] = {&h.alo[7 * k], &h.ahi[7 * k]};
+        const int ho[2] = {SP_HLO, SP_HHI}, so[2] = {SP_SLO, SP_SHI}, co[2] = {SP_CLO, SP_CHI};
+        for (int r = 0; r < 2; r++) {
+            const double* a = set[r];
+            const double hc[6] = {a[0], a[1] / 2, a[2] / 3, a[3] / 4, a[4] / 5, a[5]};
+            const double sc[6] = {a[0], a[1], a[2] / 2, a[3] / 3, a[4] / 4, a[6]};
+            for (int t = 0; t < 6; t++) {
+                q[ho[r] + t] = hc[t];
+                q[so[r] + t] = sc[t];
+            }
+            for (int t = 0; t < 5; t++) q[co[r] + t] = a[t];
+        }
+    }
+    for (int jj = 0; jj < nr; jj++) {
+        const HostReaction& r = h.rx[order[jj]];
+        double* q = &rx[(size_t)jj * RXS];
+        q[RX_LNA] = std::log(r.A);
+        q[RX_B] = r.b;
+        q[RX_EAR] = r.Ea / RGAS;
+        q[RX_LNA0] = r.type == 2 ? std::log(r.A0) : 0.0;
+        q[RX_B0] = r.b0;
+        q[RX_EA0R] = r.Ea0 / RGAS;
+        for (int t = 0; t < 4; t++) q[RX_TROE + t] = r.troe[t];
+        int* w = &rxi[(size_t)jj * RXI];
+        w[RI_TYPE] = r.type;
+        w[RI_REV] = r.rev;
+        w[RI_TROEN] = r.troe_n;
+        int dnu = 0;
+        w[RI_NRE] = (int)r.re.size();
+        w[RI_NPR] = (int)r.pr.size();
+        for (size_t i = 0; i < r.re.size(); i++) {
+            w[RI_RSP + i] = r.re[i].first;
+            w[RI_RNU + i] = r.re[i].second;
+            dnu -= r.re[i].second;
+        }
+        for (size_t i = 0; i < r.pr.size(); i++) {
+            w[RI_PSP + i] = r.pr[i].first;
+            w[RI_PNU + i] = r.pr[i].second;
+            dnu += r.pr[i].second;
+        }
+        w[RI_DNU] = dnu;
+        w[RI_EB] = (int)effs.size();
+        if (r.type != 0)
+            for (int k = 0; k < ns; k++)
+                if (r.eff[k] != 1.0) {
+                    effs.push_back(k);
+                    effa.push_back(r.eff[k] - 1.0);
+                }
+        w[RI_EE] = (int)effs.size();
+    }
+    // species -> (reaction, net nu), reactions in increasing (reordered) index
+    for (int k = 0; k < ns; k++) {
+        ptr[k] = (int)crx.size();
+        for (int jj = 0; jj < nr; jj++) {
+            const HostReaction& r = h.rx[order[jj]];
+            int nu = 0;
+            for (auto& pq : r.re)
+                if (pq.first == k) nu -= pq.second;
+            for (auto& pq : r.pr)
+                if (pq.first == k) nu += pq.second;
+            if (nu != 0) {
+                crx.push_back(jj);
+                cnu.push_back((double)nu);
+            }
+        }
+    }
+    ptr[ns] = (int)crx.size();
+    if (effs.empty()) {
+        effs.push_back(0);
+        effa.push_back(0.0);
+    }
+    if (crx.empty()) {
+        crx.push_back(0);
+        cnu.push_back(0.0);
+    }
+    auto up = [&](const void* src, size_t bytes, void** dst) -> int {
+        void* d = nullptr;
+        HIPCHK(hipMalloc(&d, bytes));
+        m->dbufs.push_back(d);
+        HIPCHK(hipMemcpy(d, src, bytes, hipMemcpyHostToDevice));
+        *dst = d;
+        return 0;
+    };
+    void *a1, *a2, *a3, *a4, *a5, *a6, *a7, *a8;
+    int rc = up(sp.data(), sp.size() * 8, &a1) || up(rx.data(), rx.size() * 8, &a2) ||
+             up(rxi.data(), rxi.size() * 4, &a3) || up(effs.data(), effs.size() * 4, &a4) ||
+             up(effa.data(), effa.size() * 8, &a5) || up(ptr.data(), ptr.size() * 4, &a6) ||
+             up(crx.data(), crx.size() * 4, &a7) || up(cnu.data(), cnu.size() * 8, &a8);
+    if (rc) return CHEM_E_HIP;
+    CoopMech& c = m->cm;
+    c.ns = ns;
+    c.nr = nr;
+    c.n = ns + 1;
+    c.sp = (const double*)a1;
+    c.rx = (const double*)a2;
+    c.rxi = (const int*)a3;
+    c.eff_sp = (const int*)a4;
+    c.eff_am1 = (const double*)a5;
+    c.csr_ptr = (const int*)a6;
+    c.csr_rx = (const int*)a7;
+    c.csr_nu = (const double*)a8;
+    return 0;
+}
+
+// cooperative schedules compiled: (G, R) with room for G*R components
+#define CHEM_COOP_SCHEDULES(X) X(4, 3) X(8, 2) X(16, 1) X(32, 2) X(64, 1)
+
+int coop_R(int G) {
+    switch (G) {
+#define X(g, r) case g: return r;
+        CHEM_COOP_SCHEDULES(X)
+#undef X
+    }
+    return 0;
+}
+
+int coop_lds_bytes(const chem_mech_s* m, int G) {
+    const int R = coop_R(G), NC = G * R;
+    const int gl = group_lds_doubles(m->hm.ns, (int)m->hm.rx.size(), NC);
+    return 8 * ((64 / G) * gl + 64 * R * NC);
+}
+
+template <int G, int R, int MODE>
+int launch_coop_one(chem_ctx_s* c, int64_t grid, const CoopArgs& a, int lds) {
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute((const void*)k_integrate_coop<G, R, MODE>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        attr = true;
+    }
+    hipLaunchKernelGGL((k_integrate_coop<G, R, MODE>), dim3(grid), dim3(64), lds, c->stream, a);
+    return 0;
+}
+
+int launch_coop(chem_ctx_s* c, int G, int mode, int64_t grid, const CoopArgs& a, int lds) {
+    switch (G) {
+#define X(g, r)                                                              \
+    case g:                                                                  \
+        if (mode == PLAIN) return launch_coop_one<g, r, PLAIN>(c, grid, a, lds); \
+        if (mode == BULK) return launch_coop_one<g, r, BULK>(c, grid, a, lds);   \
+        return launch_coop_one<g, r, SPARSE>(c, grid, a, lds);
+        CHEM_COOP_SCHEDULES(X)
+#undef X
+    }
+    return fail(CHEM_E_INVAL, "unknown cooperative schedule");
+}
+
+int coop_blocks_per_cu(chem_ctx_s* c, int G) {
+    const int lds = coop_lds_bytes(c->m, G);
+    int nb = 0;
+    hipError_t e = hipErrorInvalidValue;
+    switch (G) {
+#define X(g, r)                                                                                       \
+    case g:                                                                                           \
+        (void)hipFuncSetAttribute((const void*)k_integrate_coop<g, r, SPARSE>,                        \
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds);                  \
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_integrate_coop<g, r, SPARSE>, 64, lds); \
+        break;
+        CHEM_COOP_SCHEDULES(X)
+#undef X
+    }
+    if (e != hipSuccess || nb <= 0) nb = 1;
+    return nb;
+}
+
+// schedule actually used: 0 (compiled one-lane) or G
+int resolve_group(const chem_ctx_s* c) {
+    const int n = c->m->hm.ns + 1;
+    int G = c->opt.group;
+    if (G < 0) G = (n <= 16) ? 8 : 64;
+    if (G == 0 && !c->m->ops) G = (n <= 16) ? 8 : 64;
+    if (G > 0 && G * coop_R(G) < n) G = 64;
+    return G;
+}
+
+int prepare_ws(chem_ctx_s* c, int64_t total) {
+    const int G = resolve_group(c);
+    const int64_t cells = std::max<int64_t>(total, 1);
+    if (G == 0) {
+        const int N = c->m->hm.ns + 1;
+        return ensure_ws(c, cells, lanes_needed(c, total), onelane_slot_bytes(N), sizeof(double) * ND * N);
+    }
+    const int NC = G * coop_R(G);
+    const bool save = c->opt.algorithm == 1 && c->opt.max_rounds > 0;
+    return ensure_ws(c, cells, 1, save ? coop_slot_bytes(NC) : 8, 8);
+}
+
+CoopSave coop_save_area(chem_ctx_s* c, int NC) {
+    CoopSave s;
+    const int64_t L = c->cap_cells;
+    char* p = c->save.as<char>();
+    s.ld = L;
+    s.D = (double*)p;
+    p += sizeof(double) * ND * NC * L;
+    s.A = (double*)p;
+    p += sizeof(double) * NC * NC * L;
+    s.scal = (double*)p;
+    p += sizeof(double) * 3 * L;
+    s.ints = (int*)p;
+    return s;
+}
+
+int pipeline_coop(chem_ctx_s* c, int G, int64_t total, int nbox, double rtol, double atol) {
+    const Options& o = c->opt;
+    hipStream_t s = c->stream;
+    int rc = prepare_ws(c, total);
+    if (rc) return rc;
+    const int R = coop_R(G), NC = G * R, ngrp = 64 / G;
+    const int lds = coop_lds_bytes(c->m, G);
+    const int64_t grid = (int64_t)(o.grid_waves > 0 ? o.grid_waves : coop_blocks_per_cu(c, G)) * c->ncu;
+    const DevBox* db = c->boxes.as<DevBox>();
+    int* I = c->ints.as<int>();
+    Counters* ctr = c->ctr.as<Counters>();
+    const int64_t nb = std::max<int64_t>(1, (total + 255) / 256);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, s, I, (int64_t)I_COUNT, 0);
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, (unsigned long long*)ctr,
+                       (int64_t)(sizeof(Counters) / 8));
+    const double tmin = o.algorithm == 1 ? o.t_react_min : -1.0;
+    hipLaunchKernelGGL(k_screen_coop, dim3(nb), dim3(256), 0, s, c->m->cm, db, nbox, total, tmin,
+                       c->st_int.as<uint8_t>(), c->bcnt.as<int>());
+    CoopArgs a{};
+    a.M = c->m->cm;
+    a.boxes = db;
+    a.nbox = nbox;
+    a.st_int = c->st_int.as<uint8_t>();
+    a.active_ids = c->active.as<int>();
+    a.flag = c->flag.as<uint8_t>();
+    a.sv = coop_save_area(c, NC);
+    a.rtol = rtol;
+    a.atol = atol;
+    a.ctr = ctr;
+    a.nstar = o.nactive_star;
+    a.rounds = I + I_ROUNDS;
+    a.gl_stride = group_lds_doubles(c->m->hm.ns, (int)c->m->hm.rx.size(), NC);
+    a.nsp = c->m->hm.ns;
+    if (o.algorithm == 0) {
+        a.n_items_host = total;
+        a.kmax = o.kmax_sparse;
+        return launch_coop(c, G, PLAIN, (total + ngrp - 1) / ngrp, a, lds);
+    }
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, c->bcnt.as<int>(), (int)nb, c->boff.as<int>(), I + I_NACT);
+    hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(256), 0, s, c->st_int.as<uint8_t>(), total, c->boff.as<int>(),
+                       c->active.as<int>());
+    hipLaunchKernelGGL(k_fill_u8, dim3(std::min<int64_t>(nb, 4096)), dim3(256), 0, s, c->flag.as<uint8_t>(),
+                       std::max<int64_t>(total, 1), (uint8_t)0);
+    const int rounds = std::min(o.max_rounds, RMAX);
+    for (int r = 0; r < rounds; r++) {
+        CoopArgs b = a;
+        b.n_items_dev = I + I_NACT;
+        b.queue = I + I_Q + r;
+        b.unfinished = I + I_UNF + r;
+        b.gate = r == 0 ? I + I_NACT : I + I_UNF + r - 1;
+        b.kmax = o.kmax_bulk;
+        rc = launch_coop(c, G, BULK, grid, b, lds);
+        if (rc) return rc;
+    }
+    hipLaunchKernelGGL(k_count_unfinished, dim3(nb), dim3(256), 0, s, c->flag.as<uint8_t>(), I + I_NACT,
+                       c->bcnt.as<int>());
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, c->bcnt.as<int>(), (int)nb, c->boff.as<int>(), I + I_NSP);
+    hipLaunchKernelGGL(k_scatter_unfinished, dim3(nb), dim3(256), 0, s, c->flag.as<uint8_t>(), I + I_NACT,
+                       c->boff.as<int>(), c->sparse.as<int>());
+    CoopArgs sp = a;
+    sp.items = c->sparse.as<int>();
+    sp.n_items_dev = I + I_NSP;
+    sp.queue = I + I_Q + RMAX;
+    sp.kmax = o.kmax_sparse;
+    return launch_coop(c, G, SPARSE, grid, sp, lds);
+}
+
+int pipeline_any(chem_ctx_s* c, int64_t total, int nbox, double rtol, double atol) {
+    const int G = resolve_group(c);
+    if (G == 0) return c->m->ops->pipeline(c, total, nbox, rtol, atol);
+    return pipeline_coop(c, G, total, nbox, rtol, atol);
+}
+
+template <int G, int R>
+int eval_coop_t(chem_ctx_s* c, int64_t n, const double* rho, const double* y, double* f, double* J) {
+    const int NC = G * R, ngrp = 64 / G;
+    const int lds = coop_lds_bytes(c->m, G);
+    const int gls = group_lds_doubles(c->m->hm.ns, (int)c->m->hm.rx.size(), NC);
+    (void)hipFuncSetAttribute((const void*)k_eval_coop<G, R>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    hipLaunchKernelGGL((k_eval_coop<G, R>), dim3((n + ngrp - 1) / ngrp), dim3(64), lds, c->stream, c->m->cm,
+                       gls, c->m->hm.ns, n, rho, y, f, J);
+    HIPCHK(hipGetLastError());
+    return 0;
+}
+
+int eval_any(chem_ctx_s* c, int64_t n, const double* rho, const double* y, double* f, double* J) {
+    if (n == 0) return 0;
+    const int G = resolve_group(c);
+    if (G == 0) return c->m->ops->eval(c, n, rho, y, f, J);
+    switch (G) {
+#define X(g, r) case g: return eval_coop_t<g, r>(c, n, rho, y, f, J);
+        CHEM_COOP_SCHEDULES(X)
+#undef X
+    }
+    return fail(CHEM_E_INVAL, "unknown schedule");
+}
+
+int prepare_any(chem_ctx_s* c, int64_t n, const double* T, const double* p, const double* Y, int64_t ldY,
+                double* rho, double* e) {
+    if (n == 0) return 0;
+    hipLaunchKernelGGL(k_prepare_coop, dim3((n + 255) / 256), dim3(256), 0, c->stream, c->m->cm, n, T, p, Y, ldY,
+                       rho, e);
     HIPCHK(hipGetLastError());
     return 0;
 }
@@ -398,7 +741,7 @@ int run(chem_ctx_s* c, const std::vector<chem_box>& bx, double rtol, double atol
         if (rc) return rc;
         if (use_graph) {
             // workspace must exist before capture: run the sizing once (no kernels)
-            rc = ensure_ws(c, off, lanes_needed(c, off), c->m->hm.ns + 1);
+            rc = prepare_ws(c, off);
             if (rc) return rc;
             if (c->gexec) {
                 (void)hipGraphExecDestroy(c->gexec);
@@ -406,7 +749,7 @@ int run(chem_ctx_s* c, const std::vector<chem_box>& bx, double rtol, double atol
             }
             hipGraph_t graph = nullptr;
             HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-            rc = c->m->ops->pipeline(c, off, (int)v.size(), rtol, atol);
+            rc = pipeline_any(c, off, (int)v.size(), rtol, atol);
             hipError_t e1 = hipStreamEndCapture(c->stream, &graph);
             if (rc) return rc;
             if (e1 != hipSuccess) return fail(CHEM_E_HIP, std::string("graph capture: ") + hipGetErrorString(e1));
@@ -419,7 +762,7 @@ int run(chem_ctx_s* c, const std::vector<chem_box>& bx, double rtol, double atol
             c->g_opt = c->opt;
             HIPCHK(hipGraphLaunch(c->gexec, c->stream));
         } else {
-            rc = c->m->ops->pipeline(c, off, (int)v.size(), rtol, atol);
+            rc = pipeline_any(c, off, (int)v.size(), rtol, atol);
             if (rc) return rc;
         }
     }
@@ -451,18 +794,19 @@ int chem_load_mechanism(const char* path, chem_mech_t* out) {
     const MechOps* ops = nullptr;
     for (const auto& o : g_ops)
         if (o.hash == h.hash && o.ns == h.ns && o.nr == (int)h.rx.size()) ops = &o;
-    if (!ops) {
-        char buf[160];
-        snprintf(buf, sizeof buf, "no kernels compiled for this mechanism structure (hash %016llx); "
-                 "add it to the build's mechanism list", (unsigned long long)h.hash);
-        return fail(CHEM_E_MECH, buf);
-    }
+    if (h.ns + 1 > 64) return fail(CHEM_E_MECH, "more than 63 species are not supported");
     auto m = std::make_unique<chem_mech_s>();
     m->hm = std::move(h);
     m->ops = ops;
     if (hipGetDevice(&m->device) != hipSuccess) return fail(CHEM_E_HIP, "hipGetDevice failed");
-    int rc = ops->upload(m->hm, &m->dparams);
+    int rc = ops ? ops->upload(m->hm, &m->dparams) : 0;
     if (rc) return rc;
+    rc = upload_coop_tables(m.get());
+    if (rc) {
+        for (void* p : m->dbufs) (void)hipFree(p);
+        if (m->dparams) (void)hipFree(m->dparams);
+        return rc;
+    }
     *out = m.release();
     return CHEM_OK;
 }
@@ -484,6 +828,7 @@ int chem_species_name(chem_mech_t m, int k, const char** name) {
 void chem_free_mechanism(chem_mech_t m) {
     if (!m) return;
     if (m->dparams) (void)hipFree(m->dparams);
+    for (void* p : m->dbufs) (void)hipFree(p);
     delete m;
 }
 
@@ -532,7 +877,10 @@ int chem_set_option(chem_ctx_t c, const char* key, double v) {
     else if (k == "grid_waves" && in(0, 64)) o.grid_waves = (int)v;
     else if (k == "precision" && in(0, 0)) o.precision = (int)v;
     else if (k == "use_graph" && in(0, 1)) o.use_graph = (int)v;
-    else return fail(CHEM_E_INVAL, "unknown option or value out of range: " + k);
+    else if (k == "group" && (v == -1 || v == 0 || v == 4 || v == 8 || v == 16 || v == 32 || v == 64)) {
+        if (v == 0 && !c->m->ops) return fail(CHEM_E_INVAL, "no compiled one-lane kernel for this mechanism");
+        o.group = (int)v;
+    } else return fail(CHEM_E_INVAL, "unknown option or value out of range: " + k);
     return CHEM_OK;
 }
 
@@ -549,6 +897,7 @@ int chem_get_option(chem_ctx_t c, const char* key, double* v) {
     else if (k == "grid_waves") *v = o.grid_waves;
     else if (k == "precision") *v = o.precision;
     else if (k == "use_graph") *v = o.use_graph;
+    else if (k == "group") *v = resolve_group(c);
     else return fail(CHEM_E_INVAL, "unknown option: " + k);
     return CHEM_OK;
 }
@@ -574,13 +923,13 @@ int chem_prepare_state(chem_ctx_t c, int64_t n, const double* T, const double* p
     if (!c || n < 0 || (n > 0 && (!T || !p || !Y || !rho || !e)) || ldY < n)
         return fail(CHEM_E_INVAL, "bad arguments");
     HIPCHK(hipSetDevice(c->device));
-    return c->m->ops->prepare(c, n, T, p, Y, ldY, rho, e);
+    return prepare_any(c, n, T, p, Y, ldY, rho, e);
 }
 
 int chem_eval_rhs(chem_ctx_t c, int64_t n, const double* rho, const double* y, double* f, double* J) {
     if (!c || n < 0 || (n > 0 && (!rho || !y || !f))) return fail(CHEM_E_INVAL, "bad arguments");
     HIPCHK(hipSetDevice(c->device));
-    return c->m->ops->eval(c, n, rho, y, f, J);
+    return eval_any(c, n, rho, y, f, J);
 }
 
 int chem_load_surrogate(chem_ctx_t c, const char* path) {

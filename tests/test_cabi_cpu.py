@@ -40,10 +40,13 @@ def test_bad_mechanism_files_rejected(tmp_path):
     with pytest.raises(chem.ChemError, match="balanced") as ei:
         chem.Mechanism(str(p))
     assert ei.value.rc == -4
-    # a valid file whose structure has no compiled kernels
+    # a valid file without compiled one-lane kernels is accepted (data-driven
+    # kernels); without a GPU the load then stops at the first HIP call
     p.write_text(format_mechanism(toymech.isomer_AB()))
-    with pytest.raises(chem.ChemError, match="no kernels compiled") as ei:
+    try:
         chem.Mechanism(str(p))
+    except chem.ChemError as ex:
+        assert ex.rc == -2, str(ex)
 
 
 def test_null_arguments():

@@ -29,6 +29,10 @@ def ctx(chem, mech):
     return chem.Context(mech)
 
 
+# 0 = compiled kernel with one cell per lane; G > 0 = G lanes cooperate on a cell
+SCHEDULES = [0, 8, 16, 64]
+
+
 def test_mechanism_info(mech, m9):
     assert mech.ns == 9 and mech.nr == 21
     assert mech.species == m9.species
@@ -56,8 +60,10 @@ def _random_states(m, n, seed):
     return rho, np.vstack([Y, T[None, :]])
 
 
-def test_rhs_and_jacobian_vs_oracle(ctx, m9):
+@pytest.mark.parametrize("group", SCHEDULES)
+def test_rhs_and_jacobian_vs_oracle(chem, mech, m9, group):
     import torch
+    ctx = chem.Context(mech, group=group)
     n = 10000
     rho, y = _random_states(m9, n, 21)
     f = torch.zeros((m9.n, n), dtype=torch.float64, device="cuda")
@@ -92,16 +98,18 @@ def c1_reference(m9):
     return c, rho, e, Yr, Tr
 
 
+@pytest.mark.parametrize("group", SCHEDULES)
 @pytest.mark.parametrize("algorithm", [0, 1])
-def test_c1_parity_strict(chem, mech, c1_reference, algorithm):
+def test_c1_parity_strict(chem, mech, c1_reference, algorithm, group):
     # 1e-6 relative on every species above 1e-10 and 1e-3 K, with atol small
     # enough (1e-20) that the error control is relative on all those species
     c, rho, e, Yr, Tr = c1_reference
-    ctx = chem.Context(mech, algorithm=algorithm)
+    ctx = chem.Context(mech, algorithm=algorithm, group=group)
     Yg, Tg, st, stats = run_gpu(ctx, rho, e, c.Y, c.T, c.dt, RTOL_C1, 1e-20)
     assert stats["rc"] == 0 and np.all(st == 0), np.bincount(st)
     rel, dT, _ = parity_report(Yg, Tg, Yr, Tr)
-    print(f"C1 strict algorithm={algorithm}: max rel species err {rel:.3e}, max |dT| {dT:.3e} K")
+    print(f"C1 strict algorithm={algorithm} group={group}: max rel species err {rel:.3e}, "
+          f"max |dT| {dT:.3e} K, {stats['t_total_ms']:.2f} ms")
     assert dT <= T_ABS
     assert rel <= SPECIES_REL
 
@@ -124,7 +132,8 @@ def test_c1_parity_at_c1_tolerances(chem, mech, c1_reference, algorithm):
     assert rel_dom <= SPECIES_REL
 
 
-def test_bulk_sparse_bitwise_equals_plain(chem, mech, m9):
+@pytest.mark.parametrize("group", SCHEDULES)
+def test_bulk_sparse_bitwise_equals_plain(chem, mech, m9, group):
     # detonation-patch sample: plain all-cells vs bulk-sparse with several
     # switch points; integrated cells must agree bit for bit
     c = fields.c2_field(64, 64, 4, x_scale=1.0)
@@ -133,7 +142,7 @@ def test_bulk_sparse_bitwise_equals_plain(chem, mech, m9):
     for opts in ({"algorithm": 0}, {"algorithm": 1, "nactive_star": 0, "kmax_bulk": 3},
                  {"algorithm": 1, "nactive_star": 500, "kmax_bulk": 5},
                  {"algorithm": 1, "max_rounds": 0}):
-        ctx = chem.Context(mech, t_react_min=0.0, **opts)
+        ctx = chem.Context(mech, t_react_min=0.0, group=group, **opts)
         Yg, Tg, st, stats = run_gpu(ctx, rho, e, c.Y, c.T, c.dt, RTOL_C1, ATOL_C1)
         assert np.all(st == 0)
         if ref is None:
@@ -182,10 +191,11 @@ def test_edge_cases(chem, mech, m9):
     assert np.all(st[20:] == chem.ST_KMAX)
 
 
-def test_repeat_runs_bitwise_identical(chem, mech, m9):
+@pytest.mark.parametrize("group", SCHEDULES)
+def test_repeat_runs_bitwise_identical(chem, mech, m9, group):
     c = fields.c1_cells(2000, seed=9)
     rho, e = oracle_inputs(m9, c)
-    ctx = chem.Context(mech)
+    ctx = chem.Context(mech, group=group)
     a = run_gpu(ctx, rho, e, c.Y, c.T, c.dt, RTOL_C1, ATOL_C1)
     b = run_gpu(ctx, rho, e, c.Y, c.T, c.dt, RTOL_C1, ATOL_C1)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
