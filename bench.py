@@ -132,14 +132,37 @@ def main():
     ev_ms = ev0.elapsed_time(ev1) / args.steps
     value = n * args.steps / wall
 
-    # per-call device time of the integration (library events) and FLOPs
+    # per-call device time of each phase (library events on the context
+    # stream) and the algorithmic FLOPs of each phase
     st = step(True)
     torch.cuda.synchronize()
+    status_h = status.cpu().numpy()
     model = mech_flop_model(fields.M9_PATH)
     flops = algorithmic_flops(model, st)
-    t_call_s = st["t_total_ms"] * 1e-3
-    achieved = flops / t_call_s / 1e12
-    status_h = status.cpu().numpy()
+    bulk = {k: st["bulk_" + k] for k in ("rhs_evals", "jac_evals", "lu_facts", "lin_solves")}
+    f_bulk = algorithmic_flops(model, bulk)
+    f_sparse = flops - f_bulk
+    group = ctx.get_option("group")
+    sched = ("one lane per cell" if (group == 0 or (group < 0 and n >= 65536)) else
+             f"{int(group) if group > 0 else 16} lanes per cell")
+    if st["t_bulk_ms"] >= st["t_sparse_ms"]:
+        kern, f_k, t_k = f"bulk-round integration kernel ({sched})", f_bulk, st["t_bulk_ms"]
+    else:
+        kern, f_k, t_k = f"sparse-phase integration kernel ({sched})", f_sparse, st["t_sparse_ms"]
+    achieved = f_k / (t_k * 1e-3) / 1e12
+
+    # the same patch on the plain path (every cell, no skip, no compaction)
+    ctx_plain = chem.Context(mech, algorithm=0)
+    Y.copy_(Y0)
+    T.copy_(T_d)
+    st_plain = ctx_plain.integrate(rho, e, Y, T, cells.dt, args.rtol, args.atol, status=status)
+    # mixed precision (FP32 exponentials), same tolerances
+    ctx_mixed = chem.Context(mech, precision=1)
+    for _ in range(2):
+        Y.copy_(Y0)
+        T.copy_(T_d)
+        st_mixed = ctx_mixed.integrate(rho, e, Y, T, cells.dt, args.rtol, args.atol, status=status)
+    torch.cuda.synchronize()
     out = {
         "metric": METRIC, "value": value, "unit": "cell-steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
@@ -151,7 +174,7 @@ def main():
                    "algorithm": "bulk-sparse" if args.algorithm == 1 else "plain",
                    "options": {k: ctx.get_option(k) for k in (
                        "t_react_min", "kmax_bulk", "nactive_star", "kmax_sparse", "max_rounds",
-                       "grid_waves")}},
+                       "grid_waves", "group")}},
         "event_ms_per_step": ev_ms,
         "stats": {k: st[k] for k in ("n_active0", "n_active_after_bulk", "n_bulk_rounds",
                                      "steps_total", "attempts_total", "rhs_evals", "jac_evals",
@@ -159,8 +182,17 @@ def main():
         "status_counts": np.bincount(status_h, minlength=8).tolist(),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
-                     "kernel": "integration pipeline (bulk rounds + sparse phase)",
-                     "flops_per_call": flops, "flop_model": model},
+                     "kernel": kern, "kernel_ms_per_call": t_k, "flops_per_call": f_k,
+                     "whole_call": {"flops": flops, "ms": st["t_total_ms"],
+                                    "tflops": flops / (st["t_total_ms"] * 1e-3) / 1e12},
+                     "phase_ms": {k: st[k] for k in ("t_screen_ms", "t_bulk_ms", "t_sparse_ms")},
+                     "flop_model": model},
+        "variants": {
+            "plain_all_cells_fp64": {"ms_per_call": st_plain["t_total_ms"],
+                                     "speedup_of_bulk_sparse": st_plain["t_total_ms"] / st["t_total_ms"]},
+            "bulk_sparse_mixed_fp32_exp": {"ms_per_call": st_mixed["t_total_ms"],
+                                           "speedup_vs_fp64": st["t_total_ms"] / st_mixed["t_total_ms"]},
+        },
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cells, args, n)

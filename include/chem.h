@@ -16,7 +16,9 @@
  * Rates use the matrix form: every reaction's forward and reverse rate of
  * progress is a stoichiometric contraction against log-concentrations
  * followed by exp (Sec. 2.1, kinetics adapted from a matrix-based solver).
- * Concentrations are floored at 1e-300 mol/m^3 inside the logarithm.
+ * The contraction runs on ln|C| (|C| floored at 1e-300 mol/m^3) and the sign
+ * of a rate of progress is the parity of its negative factors with odd
+ * exponents, so negative concentrations give the plain mass-action product.
  * Integration is implicit (variable-order BDF, modified Newton with an
  * analytic Jacobian and LU with partial pivoting, FP64).  With the
  * bulk-sparse algorithm (Alg. 3) every active cell first runs rounds of at
@@ -88,6 +90,11 @@ typedef struct {
     int64_t rhs_evals, jac_evals, lu_facts, lin_solves;
     int64_t max_steps_cell;     /* most attempts spent by one cell */
     double t_total_ms;          /* device time of the call (events on the context stream) */
+    /* phase split (eager calls only; zero when the call replayed a graph):
+     * screening + compaction, bulk rounds, sparse phase (or the plain path) */
+    double t_screen_ms, t_bulk_ms, t_sparse_ms;
+    /* the part of rhs_evals .. lin_solves spent in the bulk rounds */
+    int64_t bulk_rhs_evals, bulk_jac_evals, bulk_lu_facts, bulk_lin_solves;
 } chem_stats;
 
 /* One AMR box (a separately allocated grid): device pointers, column-major
@@ -130,7 +137,12 @@ void chem_ctx_destroy(chem_ctx_t c);
  *   kmax_sparse   step limit of the sparse phase / plain path, default 1e5
  *   max_rounds    bulk-round launches enqueued per call (device decides how many run), default 24
  *   grid_waves    waves per CU of the persistent integration kernel, default 0 (auto)
- *   precision     0 = FP64 rates (default); other values reserved for mixed-precision kernels
+ *   precision     0 = FP64 rates (default); 1 = exp/log of the rate evaluation on the
+ *                 FP32 units with FP64 range reduction (Newton, LU, T inversion,
+ *                 contractions and net rates stay FP64)
+ *   group         lanes per cell: 0 = compiled one-lane kernel (if the mechanism's
+ *                 structure was compiled in), 4/8/16/32/64 = cooperative kernels,
+ *                 -1 = automatic (default)
  *   use_graph     1 = capture the enqueued pipeline of chem_integrate_boxes in a
  *                 hipGraph and replay it while the box table is unchanged, default 1
  * Returns CHEM_E_INVAL for an unknown key or out-of-range value. */
@@ -172,6 +184,17 @@ int chem_prepare_state(chem_ctx_t c, int64_t ncell, const double* T, const doubl
  * building blocks against the oracle. */
 int chem_eval_rhs(chem_ctx_t c, int64_t ncell, const double* rho, const double* y, double* f,
                   double* J);
+
+/* Autotuner: times candidate schedules (lanes per cell, bulk phase on/off,
+ * N*, persistent grid size) on the given boxes and sets the fastest as the
+ * context's options.  Y and T of every box are restored afterwards (the call
+ * synchronises the stream).  The choice is cached as a JSON line keyed by
+ * (GPU arch, mechanism structure hash, box count, cell count, rtol, atol,
+ * precision) in cache_path (NULL = no cache); a cache hit runs nothing.
+ * best_ms (may be NULL) receives the winning call time.  Errors as
+ * chem_integrate_boxes. */
+int chem_autotune(chem_ctx_t c, int nbox, const chem_box* boxes, double rtol, double atol,
+                  const char* cache_path, double* best_ms);
 
 int chem_load_surrogate(chem_ctx_t c, const char* weights_path);
 int chem_synchronize(chem_ctx_t c);

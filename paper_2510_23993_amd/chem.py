@@ -23,7 +23,9 @@ class chem_stats(C.Structure):
     _fields_ = [(n, C.c_int64) for n in (
         "ncell", "n_active0", "n_active_after_bulk", "n_bulk_rounds", "n_sparse", "n_incomplete",
         "n_fallback", "steps_total", "attempts_total", "rhs_evals", "jac_evals", "lu_facts",
-        "lin_solves", "max_steps_cell")] + [("t_total_ms", C.c_double)]
+        "lin_solves", "max_steps_cell")] + [(n, C.c_double) for n in (
+        "t_total_ms", "t_screen_ms", "t_bulk_ms", "t_sparse_ms")] + [(n, C.c_int64) for n in (
+        "bulk_rhs_evals", "bulk_jac_evals", "bulk_lu_facts", "bulk_lin_solves")]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -46,7 +48,7 @@ _lib = None
 EXPORTS = ["chem_load_mechanism", "chem_mech_info", "chem_species_name", "chem_free_mechanism",
            "chem_ctx_create", "chem_ctx_destroy", "chem_set_option", "chem_get_option",
            "chem_load_surrogate", "chem_integrate", "chem_integrate_boxes", "chem_prepare_state",
-           "chem_eval_rhs", "chem_synchronize", "chem_last_error"]
+           "chem_eval_rhs", "chem_synchronize", "chem_last_error", "chem_autotune"]
 
 
 def lib():
@@ -80,6 +82,8 @@ def lib():
     L.chem_prepare_state.argtypes = [vp, i64, vp, vp, vp, i64, vp, vp]
     L.chem_eval_rhs.argtypes = [vp, i64, vp, vp, vp, vp]
     L.chem_synchronize.argtypes = [vp]
+    L.chem_autotune.argtypes = [vp, C.c_int, C.POINTER(chem_box), dbl, dbl, C.c_char_p,
+                                C.POINTER(dbl)]
     _lib = L
     return L
 
@@ -202,6 +206,26 @@ class Context:
         d = st.as_dict()
         d["rc"] = rc
         return d
+
+    def _box_array(self, boxes):
+        arr = (chem_box * len(boxes))()
+        for i, b in enumerate(boxes):
+            n = b["rho"].shape[0]
+            _check_f64("Y", b["Y"], (self.mech.ns, n))
+            arr[i] = chem_box(n, _ptr(b["rho"]), _ptr(b["e"]), _ptr(b["Y"]), n, _ptr(b["T"]),
+                              _ptr(b.get("mask")), _ptr(b.get("status")), float(b["dt"]),
+                              int(b.get("level", 0)))
+        return arr
+
+    def autotune(self, boxes: Sequence[dict], rtol, atol, cache_path: Optional[str] = None):
+        """Pick the fastest schedule for these boxes; returns (options, ms)."""
+        arr = self._box_array(boxes)
+        ms = C.c_double()
+        _check(lib().chem_autotune(self._h, len(boxes), arr, float(rtol), float(atol),
+                                   cache_path.encode() if cache_path else None, C.byref(ms)))
+        opts = {k: self.get_option(k) for k in ("group", "max_rounds", "nactive_star",
+                                                 "kmax_bulk", "grid_waves")}
+        return opts, ms.value
 
     def prepare_state(self, T, p, Y, rho, e):
         n = T.shape[0]

@@ -27,6 +27,7 @@ constexpr int CMP = 4;   // participants per side supported by the tables
 // Device tables of one mechanism (data driven).
 struct CoopMech {
     int ns, nr, n;
+    int prec;              // 0: FP64 transcendentals; 1: FP32 exp/log with FP64 range reduction
     const double* sp;      // [ns][SPS]
     const double* rx;      // [nr][RXS]
     const int* rxi;        // [nr][RXI]
@@ -80,6 +81,28 @@ __device__ __forceinline__ double rsel(const double* a, int s) {
     return v;
 }
 
+// Transcendentals of the rate evaluation.  prec = 1 uses the FP32 hardware
+// units (v_exp_f32 / v_log_f32) on a range-reduced argument and keeps the
+// range and the reduction in FP64: relative error ~1e-7 instead of ~1e-16.
+__device__ __forceinline__ double rexp(double x, int prec) {
+    if (prec == 0) return exp(x);
+    const double t = x * 1.4426950408889634074;   // log2(e)
+    const double n = rint(t);
+    const float f = (float)(t - n);                // |f| <= 1/2
+    return ldexp((double)exp2f(f), (int)fmax(fmin(n, 2000.0), -2000.0));
+}
+// e^d - 1 for |d| < 0.35 (Taylor series to d^7; truncation below 2e-8 relative)
+__device__ __forceinline__ double expm1_small(double d) {
+    return d * (1.0 + d * (1.0 / 2 + d * (1.0 / 6 + d * (1.0 / 24 + d * (1.0 / 120 + d * (1.0 / 720 + d * (1.0 / 5040)))))));
+}
+
+__device__ __forceinline__ double rlog(double c, int prec) {   // c > 0
+    if (prec == 0) return log(c);
+    int e;
+    const double m = frexp(c, &e);                 // c = m 2^e, m in [0.5, 1)
+    return ((double)log2f((float)m) + (double)e) * 0.69314718055994530942;
+}
+
 // ------------------------------------------------------------------ thermo
 __device__ __forceinline__ void coop_thermo(const double* sp, double T, double lnT, double invT,
                                             double& h_RT, double& s_R, double& cp_R, double& dcp) {
@@ -129,11 +152,15 @@ __device__ __forceinline__ void coop_species(const CoopMech& M, const GL& gl, in
             const double* sp = M.sp + (size_t)k * SPS;
             double h, sR, cp, dcp;
             coop_thermo(sp, T, lnT, invT, h, sR, cp, dcp);
+            // ln|C| (FP64 in every mode: near equilibrium the net rates
+            // depend on differences of these logarithms); the sign of C is
+            // carried separately so that negative concentrations give the
+            // same signed powers as the plain mass-action product
             const double C = rho * y[s] * sp[SP_INVW];
-            const double Cf = fmax(C, C_FLOOR);
-            gl.lnC[k] = log(Cf);
+            const double aC = fmax(fabs(C), C_FLOOR);
+            gl.lnC[k] = log(aC);
             gl.C[k] = C;
-            gl.iC[k] = 1.0 / Cf;
+            gl.iC[k] = (C < 0.0) ? -1.0 / aC : 1.0 / aC;
             gl.g[k] = h - sR;
             gl.h[k] = h;
             gl.cv[k] = cp - 1.0;
@@ -167,23 +194,23 @@ __device__ __forceinline__ void coop_reactions(const CoopMech& M, const GL& gl, 
         if (type == RX_FO) {
             const double lnk0 = rx[RX_LNA0] + rx[RX_B0] * lnT - rx[RX_EA0R] * invT;
             const double dlnk0 = (rx[RX_B0] + rx[RX_EA0R] * invT) * invT;
-            const double Pr = fmax(exp(lnk0 - lnkinf) * Mc, 1e-300);
-            const double lnPr = log(Pr);
+            const double Pr = fmax(rexp(lnk0 - lnkinf, M.prec) * Mc, 1e-300);
+            const double lnPr = rlog(Pr, M.prec);
             double lnF = 0.0, dlnF_dlnPr = 0.0, dlnF_dT = 0.0;
             const int tn = ri[RI_TROEN];
             if (tn > 0) {
                 const double a = rx[RX_TROE], T3 = rx[RX_TROE + 1], T1 = rx[RX_TROE + 2];
                 const double T = 1.0 / invT;
-                const double e3 = exp(-T / T3), e1 = exp(-T / T1);
+                const double e3 = rexp(-T / T3, M.prec), e1 = rexp(-T / T1, M.prec);
                 double Fc = (1.0 - a) * e3 + a * e1;
                 double dFc = -(1.0 - a) / T3 * e3 - a / T1 * e1;
                 if (tn == 4) {
                     const double T2 = rx[RX_TROE + 3];
-                    const double e2 = exp(-T2 * invT);
+                    const double e2 = rexp(-T2 * invT, M.prec);
                     Fc += e2;
                     dFc += T2 * invT * invT * e2;
                 }
-                const double phi = log(Fc) * C_INV_LN10;
+                const double phi = rlog(Fc, M.prec) * C_INV_LN10;
                 const double c = -0.4 - 0.67 * phi, nn = 0.75 - 1.27 * phi;
                 const double u = lnPr * C_INV_LN10 + c;
                 const double den = nn - 0.14 * u;
@@ -199,7 +226,7 @@ __device__ __forceinline__ void coop_reactions(const CoopMech& M, const GL& gl, 
                 }
             }
             const double ip = 1.0 / (1.0 + Pr);
-            lnkf = lnkinf + lnPr + log(ip) + lnF;   // ln(kinf Pr/(1+Pr) F)
+            lnkf = lnkinf + lnPr - rlog(1.0 + Pr, M.prec) + lnF;   // ln(kinf Pr/(1+Pr) F)
             if (JAC) {
                 const double dlnPr_dT = dlnk0 - dlnkinf;
                 dlnkf_dlnM = ip + dlnF_dlnPr;
@@ -207,19 +234,26 @@ __device__ __forceinline__ void coop_reactions(const CoopMech& M, const GL& gl, 
             }
         }
         const int nre = ri[RI_NRE], npr = ri[RI_NPR];
-        double lnqf = lnkf;   // ln qf = ln kf + nu' . ln C
-        for (int i = 0; i < nre; i++) lnqf += ri[RI_RNU + i] * gl.lnC[ri[RI_RSP + i]];
-        const double qf = exp(lnqf);
-        double qr = 0.0, dlnKc = 0.0;
+        double lnqf = lnkf;   // ln|qf| = ln kf + nu' . ln|C|; sign = parity of negative factors
+        int negf = 0;
+        for (int i = 0; i < nre; i++) {
+            const int k = ri[RI_RSP + i], nu = ri[RI_RNU + i];
+            lnqf += nu * gl.lnC[k];
+            negf ^= (nu & 1) & (gl.C[k] < 0.0);
+        }
+        const double qf = negf ? -rexp(lnqf, M.prec) : rexp(lnqf, M.prec);
+        double qr = 0.0, dlnKc = 0.0, net = qf;
         if (ri[RI_REV]) {
-            // ln Kc = -nu . g/RT + dnu ln(Pref/RT);  ln qr = ln kf - ln Kc + nu'' . ln C
+            // ln Kc = -nu . g/RT + dnu ln(Pref/RT);  ln|qr| = ln kf - ln Kc + nu'' . ln|C|
             double sg = 0.0, sh = 0.0, lnqr = lnkf;
+            int negr = 0;
             for (int i = 0; i < npr; i++) {
-                const int k = ri[RI_PSP + i];
-                const double nu = ri[RI_PNU + i];
+                const int k = ri[RI_PSP + i], inu = ri[RI_PNU + i];
+                const double nu = inu;
                 sg += nu * gl.g[k];
                 sh += nu * gl.h[k];
                 lnqr += nu * gl.lnC[k];
+                negr ^= (inu & 1) & (gl.C[k] < 0.0);
             }
             for (int i = 0; i < nre; i++) {
                 const int k = ri[RI_RSP + i];
@@ -228,11 +262,19 @@ __device__ __forceinline__ void coop_reactions(const CoopMech& M, const GL& gl, 
                 sh -= nu * gl.h[k];
             }
             const double lnKc = -sg + ri[RI_DNU] * lnPref;
-            qr = exp(lnqr - lnKc);
+            lnqr -= lnKc;
+            qr = negr ? -rexp(lnqr, M.prec) : rexp(lnqr, M.prec);
             dlnKc = (sh - ri[RI_DNU]) * invT;   // d(g/RT)/dT = -h/(R T^2)
+            net = qf - qr;
+            // FP32 exponentials carry ~1e-7 relative error each, which the
+            // difference would amplify near equilibrium: there the net rate is
+            // formed as -qf expm1(ln qr - ln qf) with the FP64 log ratio
+            if (M.prec != 0 && negf == negr) {
+                const double d = lnqr - lnqf;
+                if (fabs(d) < 0.35) net = -qf * expm1_small(d);
+            }
         }
         const double mul = (type == RX_TB) ? Mc : 1.0;
-        const double net = qf - qr;
         double* qj = gl.q + 5 * j;
         qj[4] = mul * net;
         if (JAC) {
@@ -1072,14 +1114,15 @@ __global__ void __launch_bounds__(64, 2) k_integrate_coop(CoopArgs a) {
                              s3 = wsum(L.n_jac), s4 = wsum(L.n_lu), s5 = wsum(L.n_solve),
                              s6 = wmax(max_att), s7 = wsum(incomplete), s8 = wsum(unfinished);
     if (lane == 0) {
-        atomicAdd(&a.ctr->steps, s0);
-        atomicAdd(&a.ctr->attempts, s1);
-        atomicAdd(&a.ctr->rhs, s2);
-        atomicAdd(&a.ctr->jac, s3);
-        atomicAdd(&a.ctr->lu, s4);
-        atomicAdd(&a.ctr->solves, s5);
-        atomicMax(&a.ctr->max_attempts, s6);
-        atomicAdd(&a.ctr->incomplete, s7);
+        Counters* ct = a.ctr + (MODE == BULK ? 1 : 0);   // [0] sparse or plain, [1] bulk rounds
+        atomicAdd(&ct->steps, s0);
+        atomicAdd(&ct->attempts, s1);
+        atomicAdd(&ct->rhs, s2);
+        atomicAdd(&ct->jac, s3);
+        atomicAdd(&ct->lu, s4);
+        atomicAdd(&ct->solves, s5);
+        atomicMax(&ct->max_attempts, s6);
+        atomicAdd(&ct->incomplete, s7);
         if (MODE == BULK && s8) atomicAdd(a.unfinished, (int)s8);
     }
 }

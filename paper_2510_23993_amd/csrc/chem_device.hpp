@@ -180,6 +180,7 @@ template <class M>
 struct CellEval {
     double C[M::NS], lnC[M::NS], h_RT[M::NS], g_RT[M::NS];
     double lnT, invT, lnPref;
+    uint64_t neg;   // bit k set: C_k < 0
 };
 
 template <class M>
@@ -189,10 +190,15 @@ __device__ __forceinline__ void cell_eval(const Params<M>& P, double rho, const 
     E.lnT = log(T);
     E.invT = 1.0 / T;
     E.lnPref = LN_PREF_OVER_R - E.lnT;
+    // ln|C| with the sign kept aside: negative concentrations then give the
+    // signed integer powers of the plain mass-action product
+    static_assert(M::NS <= 64, "sign mask holds 64 species");
+    E.neg = 0;
 #pragma unroll
     for (int k = 0; k < M::NS; k++) {
         E.C[k] = rho * y[k] * P.invW[k];
-        E.lnC[k] = log(fmax(E.C[k], C_FLOOR));
+        E.lnC[k] = log(fmax(fabs(E.C[k]), C_FLOOR));
+        E.neg |= (uint64_t)(E.C[k] < 0.0) << k;
     }
     thermo_hg(P, T, E.lnT, E.invT, E.h_RT, E.g_RT);
 }
@@ -201,10 +207,19 @@ __device__ __forceinline__ void cell_eval(const Params<M>& P, double rho, const 
 // (forward: nu'; reverse: nu'' minus the ln Kc row).
 template <class M, int j>
 __device__ __forceinline__ void rxn_lnq(const CellEval<M>& E, double lnkf, double& lnqf,
-                                        double& lnqr) {
+                                        double& lnqr, double& sf, double& sr) {
     lnqf = lnkf;
+    uint64_t pf = 0, pr = 0;   // parity of the negative factors with odd exponents
 #pragma unroll
-    for (int i = 0; i < M::NRE[j]; i++) lnqf += M::RNU[j][i] * E.lnC[M::RSP[j][i]];
+    for (int i = 0; i < M::NRE[j]; i++) {
+        lnqf += M::RNU[j][i] * E.lnC[M::RSP[j][i]];
+        if (M::RNU[j][i] & 1) pf ^= E.neg >> M::RSP[j][i];
+    }
+#pragma unroll
+    for (int i = 0; i < M::NPR[j]; i++)
+        if (M::PNU[j][i] & 1) pr ^= E.neg >> M::PSP[j][i];
+    sf = (pf & 1) ? -1.0 : 1.0;
+    sr = (pr & 1) ? -1.0 : 1.0;
     lnqr = -1e300;
     if (M::REV[j]) {
         double sg = 0.0;  // sum_k nu_kj g_k/RT
@@ -224,10 +239,10 @@ __device__ __forceinline__ void rhs_loop(const Params<M>& P, const CellEval<M>& 
     if constexpr (j < M::NR) {
         RxnK r;
         rxn_k<M, j>(P, E.lnT, E.invT, E.C, r, false);
-        double lnqf, lnqr;
-        rxn_lnq<M, j>(E, r.lnkf, lnqf, lnqr);
-        double q = exp(lnqf);
-        if (M::REV[j]) q -= exp(lnqr);
+        double lnqf, lnqr, sf, sr;
+        rxn_lnq<M, j>(E, r.lnkf, lnqf, lnqr, sf, sr);
+        double q = sf * exp(lnqf);
+        if (M::REV[j]) q -= sr * exp(lnqr);
         if (M::TYPE[j] == RX_TB) q *= r.M;
 #pragma unroll
         for (int i = 0; i < M::NRE[j]; i++) om[M::RSP[j][i]] -= M::RNU[j][i] * q;
@@ -276,10 +291,10 @@ __device__ __forceinline__ void jac_loop(const Params<M>& P, const CellEval<M>& 
         constexpr int TY = M::TYPE[j];
         RxnK r;
         rxn_k<M, j>(P, E.lnT, E.invT, E.C, r, true);
-        double lnqf, lnqr;
-        rxn_lnq<M, j>(E, r.lnkf, lnqf, lnqr);
-        const double qf = exp(lnqf);
-        const double qr = M::REV[j] ? exp(lnqr) : 0.0;
+        double lnqf, lnqr, sf, sr;
+        rxn_lnq<M, j>(E, r.lnkf, lnqf, lnqr, sf, sr);
+        const double qf = sf * exp(lnqf);
+        const double qr = M::REV[j] ? sr * exp(lnqr) : 0.0;
         const double mul = (TY == RX_TB) ? r.M : 1.0;
         const double net = qf - qr;
         // d ln qf/dT = dlnkf, d ln qr/dT = dlnkf - dlnKc
@@ -347,7 +362,8 @@ __device__ __forceinline__ void jac_eval(const Params<M>& P, double rho, const d
     double invC[NS], uk[NS], om[NS], dwT[NS], dSm[NS];
 #pragma unroll
     for (int k = 0; k < NS; k++) {
-        invC[k] = 1.0 / fmax(E.C[k], C_FLOOR);
+        const double aC = fmax(fabs(E.C[k]), C_FLOOR);
+        invC[k] = (E.C[k] < 0.0) ? -1.0 / aC : 1.0 / aC;
         uk[k] = (E.h_RT[k] - 1.0) * T;  // u_k / R (molar)
         om[k] = dwT[k] = dSm[k] = 0.0;
     }

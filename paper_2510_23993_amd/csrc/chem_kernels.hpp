@@ -708,14 +708,15 @@ __global__ void __launch_bounds__(64) k_integrate(const Params<M>* __restrict__ 
                              s3 = wsum(L.n_jac), s4 = wsum(L.n_lu), s5 = wsum(L.n_solve),
                              s6 = wmax(max_att), s7 = wsum(incomplete), s8 = wsum(unfinished);
     if (lane == 0) {
-        atomicAdd(&a.ctr->steps, s0);
-        atomicAdd(&a.ctr->attempts, s1);
-        atomicAdd(&a.ctr->rhs, s2);
-        atomicAdd(&a.ctr->jac, s3);
-        atomicAdd(&a.ctr->lu, s4);
-        atomicAdd(&a.ctr->solves, s5);
-        atomicMax(&a.ctr->max_attempts, s6);
-        atomicAdd(&a.ctr->incomplete, s7);
+        Counters* ct = a.ctr + (MODE == BULK ? 1 : 0);   // [0] sparse or plain, [1] bulk rounds
+        atomicAdd(&ct->steps, s0);
+        atomicAdd(&ct->attempts, s1);
+        atomicAdd(&ct->rhs, s2);
+        atomicAdd(&ct->jac, s3);
+        atomicAdd(&ct->lu, s4);
+        atomicAdd(&ct->solves, s5);
+        atomicMax(&ct->max_attempts, s6);
+        atomicAdd(&ct->incomplete, s7);
         if (MODE == BULK && s8) atomicAdd(a.unfinished, (int)s8);
     }
 }

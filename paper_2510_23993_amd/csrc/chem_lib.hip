@@ -114,6 +114,8 @@ struct chem_ctx_s {
     DevBox* h_boxes = nullptr;  // pinned staging of the box table
     size_t h_boxes_cap = 0;
     hipEvent_t ev_copy = nullptr, ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t evp[3] = {nullptr, nullptr, nullptr};   // bulk start, bulk end, sparse start
+    bool timing = false;                                 // record evp (eager calls with stats)
     // graph cache for chem_integrate_boxes
     hipGraphExec_t gexec = nullptr;
     std::vector<chem_box> gkey;
@@ -185,7 +187,7 @@ int ensure_ws(chem_ctx_s* c, int64_t cells, int64_t lanes, size_t per_slot, size
     void* before[5] = {c->st_int.p, c->active.p, c->save.p, c->laneD.p, c->bcnt.p};
     if (c->st_int.grow(cells) || c->active.grow(cells * 4) || c->sparse.grow(cells * 4) ||
         c->flag.grow(cells) || c->bcnt.grow(nb * 4) || c->boff.grow(nb * 4) ||
-        c->ints.grow(I_COUNT * 4) || c->ctr.grow(sizeof(Counters)))
+        c->ints.grow(I_COUNT * 4) || c->ctr.grow(2 * sizeof(Counters)))
         return fail(CHEM_E_NOMEM, "workspace allocation failed");
     if (c->save.grow(per_slot * (size_t)cells)) return fail(CHEM_E_NOMEM, "save-area allocation failed");
     c->cap_cells = cells;
@@ -229,6 +231,11 @@ int64_t lanes_needed(chem_ctx_s* c, int64_t total) {
     return std::max<int64_t>(persistent_grid(c) * 64, c->opt.algorithm == 0 ? ((total + 63) / 64) * 64 : 0);
 }
 
+// phase boundary event (eager calls that return statistics only)
+void mark(chem_ctx_s* c, int i) {
+    if (c->timing) (void)hipEventRecord(c->evp[i], c->stream);
+}
+
 template <class M>
 int pipeline(chem_ctx_s* c, int64_t total, int nbox, double rtol, double atol) {
     constexpr int N = M::N;
@@ -245,7 +252,7 @@ int pipeline(chem_ctx_s* c, int64_t total, int nbox, double rtol, double atol) {
     const int64_t nb = std::max<int64_t>(1, (total + 255) / 256);
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, s, I, (int64_t)I_COUNT, 0);
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, (unsigned long long*)ctr,
-                       (int64_t)(sizeof(Counters) / 8));
+                       (int64_t)(2 * sizeof(Counters) / 8));
     const double tmin = o.algorithm == 1 ? o.t_react_min : -1.0;
     hipLaunchKernelGGL((k_screen<M>), dim3(nb), dim3(256), 0, s, P, db, nbox, total, tmin,
                        c->st_int.as<uint8_t>(), c->bcnt.as<int>());
@@ -266,6 +273,7 @@ int pipeline(chem_ctx_s* c, int64_t total, int nbox, double rtol, double atol) {
     if (o.algorithm == 0) {
         a.n_items_host = total;
         a.kmax = o.kmax_sparse;
+        mark(c, 2);
         hipLaunchKernelGGL((k_integrate<M, PLAIN>), dim3((total + 63) / 64), dim3(64), 0, s, P, a);
         return 0;
     }
@@ -275,6 +283,7 @@ int pipeline(chem_ctx_s* c, int64_t total, int nbox, double rtol, double atol) {
     hipLaunchKernelGGL(k_fill_u8, dim3(std::min<int64_t>(nb, 4096)), dim3(256), 0, s, c->flag.as<uint8_t>(),
                        std::max<int64_t>(total, 1), (uint8_t)0);
     const int rounds = std::min(o.max_rounds, RMAX);
+    mark(c, 0);
     for (int r = 0; r < rounds; r++) {
         IntArgs b = a;
         b.n_items_dev = I + I_NACT;
@@ -284,6 +293,7 @@ int pipeline(chem_ctx_s* c, int64_t total, int nbox, double rtol, double atol) {
         b.kmax = o.kmax_bulk;
         hipLaunchKernelGGL((k_integrate<M, BULK>), dim3(grid), dim3(64), 0, s, P, b);
     }
+    mark(c, 1);
     hipLaunchKernelGGL(k_count_unfinished, dim3(nb), dim3(256), 0, s, c->flag.as<uint8_t>(), I + I_NACT,
                        c->bcnt.as<int>());
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, c->bcnt.as<int>(), (int)nb, c->boff.as<int>(), I + I_NSP);
@@ -294,6 +304,7 @@ int pipeline(chem_ctx_s* c, int64_t total, int nbox, double rtol, double atol) {
     sp.n_items_dev = I + I_NSP;
     sp.queue = I + I_Q + RMAX;
     sp.kmax = o.kmax_sparse;
+    mark(c, 2);
     hipLaunchKernelGGL((k_integrate<M, SPARSE>), dim3(grid), dim3(64), 0, s, P, sp);
     return 0;
 }
@@ -428,6 +439,7 @@ int upload_coop_tables(chem_mech_s* m) {
              up(crx.data(), crx.size() * 4, &a7) || up(cnu.data(), cnu.size() * 8, &a8);
     if (rc) return CHEM_E_HIP;
     CoopMech& c = m->cm;
+    c.prec = 0;
     c.ns = ns;
     c.nr = nr;
     c.n = ns + 1;
@@ -503,18 +515,23 @@ int coop_blocks_per_cu(chem_ctx_s* c, int G) {
     return nb;
 }
 
-// schedule actually used: 0 (compiled one-lane) or G
-int resolve_group(const chem_ctx_s* c) {
+// Schedule actually used for a call over `total` cells: 0 (compiled one-lane)
+// or G lanes per cell.  Automatic choice: the one-lane kernel needs about
+// 64K cells in flight to fill 256 CUs, below that G lanes per cell give the
+// parallelism (16 for up to 16 state components, 64 above).
+constexpr int64_t ONE_LANE_MIN_CELLS = 65536;
+int resolve_group(const chem_ctx_s* c, int64_t total) {
     const int n = c->m->hm.ns + 1;
+    const int coop = (n <= 16) ? 16 : 64;
     int G = c->opt.group;
-    if (G < 0) G = (n <= 16) ? 8 : 64;
-    if (G == 0 && !c->m->ops) G = (n <= 16) ? 8 : 64;
+    if (G < 0) G = (c->m->ops && c->opt.precision == 0 && total >= ONE_LANE_MIN_CELLS) ? 0 : coop;
+    if (G == 0 && (!c->m->ops || c->opt.precision != 0)) G = coop;
     if (G > 0 && G * coop_R(G) < n) G = 64;
     return G;
 }
 
 int prepare_ws(chem_ctx_s* c, int64_t total) {
-    const int G = resolve_group(c);
+    const int G = resolve_group(c, total);
     const int64_t cells = std::max<int64_t>(total, 1);
     if (G == 0) {
         const int N = c->m->hm.ns + 1;
@@ -554,12 +571,13 @@ int pipeline_coop(chem_ctx_s* c, int G, int64_t total, int nbox, double rtol, do
     const int64_t nb = std::max<int64_t>(1, (total + 255) / 256);
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, s, I, (int64_t)I_COUNT, 0);
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, (unsigned long long*)ctr,
-                       (int64_t)(sizeof(Counters) / 8));
+                       (int64_t)(2 * sizeof(Counters) / 8));
     const double tmin = o.algorithm == 1 ? o.t_react_min : -1.0;
     hipLaunchKernelGGL(k_screen_coop, dim3(nb), dim3(256), 0, s, c->m->cm, db, nbox, total, tmin,
                        c->st_int.as<uint8_t>(), c->bcnt.as<int>());
     CoopArgs a{};
     a.M = c->m->cm;
+    a.M.prec = o.precision;
     a.boxes = db;
     a.nbox = nbox;
     a.st_int = c->st_int.as<uint8_t>();
@@ -576,6 +594,7 @@ int pipeline_coop(chem_ctx_s* c, int G, int64_t total, int nbox, double rtol, do
     if (o.algorithm == 0) {
         a.n_items_host = total;
         a.kmax = o.kmax_sparse;
+        mark(c, 2);
         return launch_coop(c, G, PLAIN, (total + ngrp - 1) / ngrp, a, lds);
     }
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, c->bcnt.as<int>(), (int)nb, c->boff.as<int>(), I + I_NACT);
@@ -584,6 +603,7 @@ int pipeline_coop(chem_ctx_s* c, int G, int64_t total, int nbox, double rtol, do
     hipLaunchKernelGGL(k_fill_u8, dim3(std::min<int64_t>(nb, 4096)), dim3(256), 0, s, c->flag.as<uint8_t>(),
                        std::max<int64_t>(total, 1), (uint8_t)0);
     const int rounds = std::min(o.max_rounds, RMAX);
+    mark(c, 0);
     for (int r = 0; r < rounds; r++) {
         CoopArgs b = a;
         b.n_items_dev = I + I_NACT;
@@ -594,6 +614,7 @@ int pipeline_coop(chem_ctx_s* c, int G, int64_t total, int nbox, double rtol, do
         rc = launch_coop(c, G, BULK, grid, b, lds);
         if (rc) return rc;
     }
+    mark(c, 1);
     hipLaunchKernelGGL(k_count_unfinished, dim3(nb), dim3(256), 0, s, c->flag.as<uint8_t>(), I + I_NACT,
                        c->bcnt.as<int>());
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, c->bcnt.as<int>(), (int)nb, c->boff.as<int>(), I + I_NSP);
@@ -604,11 +625,12 @@ int pipeline_coop(chem_ctx_s* c, int G, int64_t total, int nbox, double rtol, do
     sp.n_items_dev = I + I_NSP;
     sp.queue = I + I_Q + RMAX;
     sp.kmax = o.kmax_sparse;
+    mark(c, 2);
     return launch_coop(c, G, SPARSE, grid, sp, lds);
 }
 
 int pipeline_any(chem_ctx_s* c, int64_t total, int nbox, double rtol, double atol) {
-    const int G = resolve_group(c);
+    const int G = resolve_group(c, total);
     if (G == 0) return c->m->ops->pipeline(c, total, nbox, rtol, atol);
     return pipeline_coop(c, G, total, nbox, rtol, atol);
 }
@@ -619,7 +641,9 @@ int eval_coop_t(chem_ctx_s* c, int64_t n, const double* rho, const double* y, do
     const int lds = coop_lds_bytes(c->m, G);
     const int gls = group_lds_doubles(c->m->hm.ns, (int)c->m->hm.rx.size(), NC);
     (void)hipFuncSetAttribute((const void*)k_eval_coop<G, R>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    hipLaunchKernelGGL((k_eval_coop<G, R>), dim3((n + ngrp - 1) / ngrp), dim3(64), lds, c->stream, c->m->cm,
+    CoopMech cm = c->m->cm;
+    cm.prec = c->opt.precision;
+    hipLaunchKernelGGL((k_eval_coop<G, R>), dim3((n + ngrp - 1) / ngrp), dim3(64), lds, c->stream, cm,
                        gls, c->m->hm.ns, n, rho, y, f, J);
     HIPCHK(hipGetLastError());
     return 0;
@@ -627,7 +651,7 @@ int eval_coop_t(chem_ctx_s* c, int64_t n, const double* rho, const double* y, do
 
 int eval_any(chem_ctx_s* c, int64_t n, const double* rho, const double* y, double* f, double* J) {
     if (n == 0) return 0;
-    const int G = resolve_group(c);
+    const int G = resolve_group(c, n);
     if (G == 0) return c->m->ops->eval(c, n, rho, y, f, J);
     switch (G) {
 #define X(g, r) case g: return eval_coop_t<g, r>(c, n, rho, y, f, J);
@@ -673,12 +697,40 @@ int finish_stats(chem_ctx_s* c, int64_t total, chem_stats* st) {
     HIPCHK(hipEventRecord(c->ev1, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     int I[I_COUNT];
-    Counters ct;
+    Counters cp[2];   // [0] sparse phase or plain path, [1] bulk rounds
     HIPCHK(hipMemcpy(I, c->ints.p, sizeof(I), hipMemcpyDeviceToHost));
-    HIPCHK(hipMemcpy(&ct, c->ctr.p, sizeof(ct), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(cp, c->ctr.p, sizeof(cp), hipMemcpyDeviceToHost));
+    Counters ct = cp[0];
+    ct.steps += cp[1].steps;
+    ct.attempts += cp[1].attempts;
+    ct.rhs += cp[1].rhs;
+    ct.jac += cp[1].jac;
+    ct.lu += cp[1].lu;
+    ct.solves += cp[1].solves;
+    ct.max_attempts = std::max(ct.max_attempts, cp[1].max_attempts);
+    ct.incomplete += cp[1].incomplete;
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
     memset(st, 0, sizeof(*st));
+    st->bulk_rhs_evals = (int64_t)cp[1].rhs;
+    st->bulk_jac_evals = (int64_t)cp[1].jac;
+    st->bulk_lu_facts = (int64_t)cp[1].lu;
+    st->bulk_lin_solves = (int64_t)cp[1].solves;
+    if (c->timing) {
+        float a = 0.f, b = 0.f;
+        const bool bulk = c->opt.algorithm == 1 && c->opt.max_rounds > 0;
+        if (bulk) {
+            HIPCHK(hipEventElapsedTime(&a, c->evp[0], c->evp[1]));
+            HIPCHK(hipEventElapsedTime(&b, c->ev0, c->evp[0]));
+        } else {
+            HIPCHK(hipEventElapsedTime(&b, c->ev0, c->evp[2]));
+        }
+        st->t_screen_ms = b;
+        st->t_bulk_ms = a;
+        float sp = 0.f;
+        HIPCHK(hipEventElapsedTime(&sp, c->evp[2], c->ev1));
+        st->t_sparse_ms = sp;
+    }
     st->ncell = total;
     st->n_active0 = c->opt.algorithm == 1 ? I[I_NACT] : -1;
     st->n_active_after_bulk = c->opt.algorithm == 1 ? I[I_NSP] : -1;
@@ -730,23 +782,28 @@ int run(chem_ctx_s* c, const std::vector<chem_box>& bx, double rtol, double atol
         }
         return 0;
     }
-    const bool use_graph = allow_graph && c->opt.use_graph;
+    // the legacy null stream cannot be captured: such contexts run eagerly
+    const bool use_graph = allow_graph && c->opt.use_graph && c->stream != nullptr;
+    c->timing = st != nullptr && !use_graph;
     const bool hit = use_graph && c->gexec && c->gkey.size() == bx.size() && c->g_rtol == rtol &&
                      c->g_atol == atol && c->g_opt == c->opt &&
                      !memcmp(c->gkey.data(), bx.data(), bx.size() * sizeof(chem_box));
     if (hit) {
         HIPCHK(hipGraphLaunch(c->gexec, c->stream));
     } else {
+        // the cached graph reads the staged device box table: any re-staging
+        // (another table, or a chem_integrate call in between) invalidates it
+        if (c->gexec) {
+            (void)hipGraphExecDestroy(c->gexec);
+            c->gexec = nullptr;
+            c->gkey.clear();
+        }
         int rc = stage_boxes(c, v);
         if (rc) return rc;
         if (use_graph) {
             // workspace must exist before capture: run the sizing once (no kernels)
             rc = prepare_ws(c, off);
             if (rc) return rc;
-            if (c->gexec) {
-                (void)hipGraphExecDestroy(c->gexec);
-                c->gexec = nullptr;
-            }
             hipGraph_t graph = nullptr;
             HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
             rc = pipeline_any(c, off, (int)v.size(), rtol, atol);
@@ -847,6 +904,7 @@ int chem_ctx_create(chem_mech_t m, int device, void* stream, chem_ctx_t* out) {
     HIPCHK(hipEventCreateWithFlags(&c->ev_copy, hipEventDisableTiming));
     HIPCHK(hipEventCreate(&c->ev0));
     HIPCHK(hipEventCreate(&c->ev1));
+    for (auto& e : c->evp) HIPCHK(hipEventCreate(&e));
     HIPCHK(hipEventRecord(c->ev_copy, c->stream));
     *out = c.release();
     return CHEM_OK;
@@ -860,6 +918,8 @@ void chem_ctx_destroy(chem_ctx_t c) {
     if (c->ev_copy) (void)hipEventDestroy(c->ev_copy);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
+    for (auto e : c->evp)
+        if (e) (void)hipEventDestroy(e);
     delete c;
 }
 
@@ -875,7 +935,7 @@ int chem_set_option(chem_ctx_t c, const char* key, double v) {
     else if (k == "kmax_sparse" && in(1, 2e9)) o.kmax_sparse = (int)v;
     else if (k == "max_rounds" && in(0, RMAX)) o.max_rounds = (int)v;
     else if (k == "grid_waves" && in(0, 64)) o.grid_waves = (int)v;
-    else if (k == "precision" && in(0, 0)) o.precision = (int)v;
+    else if (k == "precision" && in(0, 1)) o.precision = (int)v;
     else if (k == "use_graph" && in(0, 1)) o.use_graph = (int)v;
     else if (k == "group" && (v == -1 || v == 0 || v == 4 || v == 8 || v == 16 || v == 32 || v == 64)) {
         if (v == 0 && !c->m->ops) return fail(CHEM_E_INVAL, "no compiled one-lane kernel for this mechanism");
@@ -897,7 +957,7 @@ int chem_get_option(chem_ctx_t c, const char* key, double* v) {
     else if (k == "grid_waves") *v = o.grid_waves;
     else if (k == "precision") *v = o.precision;
     else if (k == "use_graph") *v = o.use_graph;
-    else if (k == "group") *v = resolve_group(c);
+    else if (k == "group") *v = o.group;
     else return fail(CHEM_E_INVAL, "unknown option: " + k);
     return CHEM_OK;
 }
@@ -941,6 +1001,144 @@ int chem_load_surrogate(chem_ctx_t c, const char* path) {
 int chem_synchronize(chem_ctx_t c) {
     if (!c) return fail(CHEM_E_INVAL, "NULL context");
     HIPCHK(hipStreamSynchronize(c->stream));
+    return CHEM_OK;
+}
+
+
+// Autotuner: time candidate schedules on the caller's own boxes and keep the
+// fastest.  Inputs are copied once to a device scratch buffer, restored before
+// every trial and after the last one, so the call leaves Y and T unchanged.
+// The choice is cached as one JSON line per key in cache_path (may be NULL).
+int chem_autotune(chem_ctx_t c, int nbox, const chem_box* boxes, double rtol, double atol,
+                  const char* cache_path, double* best_ms) {
+    if (!c || nbox <= 0 || !boxes) return fail(CHEM_E_INVAL, "bad box table");
+    HIPCHK(hipSetDevice(c->device));
+    const int ns = c->m->hm.ns;
+    int64_t total = 0;
+    for (int b = 0; b < nbox; b++) {
+        int rc = check_box(boxes[b], ns);
+        if (rc) return rc;
+        total += boxes[b].ncell;
+    }
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, c->device));
+    char key[256];
+    snprintf(key, sizeof key, "%s|%016llx|%d|%lld|%g|%g|%d", prop.gcnArchName,
+             (unsigned long long)c->m->hm.hash, nbox, (long long)total, rtol, atol, c->opt.precision);
+    // cached choice?
+    if (cache_path) {
+        FILE* f = fopen(cache_path, "r");
+        if (f) {
+            char line[1024];
+            while (fgets(line, sizeof line, f)) {
+                const char* kp = strstr(line, "\"key\": \"");
+                if (!kp) continue;
+                kp += 8;
+                if (strncmp(kp, key, strlen(key)) != 0 || kp[strlen(key)] != '"') continue;
+                int g, mr, ns_, kb, gw;
+                double ms;
+                const char* op = strstr(line, "\"group\": ");
+                if (op && sscanf(op, "\"group\": %d, \"max_rounds\": %d, \"nactive_star\": %d, \"kmax_bulk\": %d, "
+                                 "\"grid_waves\": %d, \"ms\": %lf", &g, &mr, &ns_, &kb, &gw, &ms) == 6) {
+                    c->opt.group = g;
+                    c->opt.max_rounds = mr;
+                    c->opt.nactive_star = ns_;
+                    c->opt.kmax_bulk = kb;
+                    c->opt.grid_waves = gw;
+                    if (best_ms) *best_ms = ms;
+                    fclose(f);
+                    return CHEM_OK;
+                }
+            }
+            fclose(f);
+        }
+    }
+    // device copy of every box's Y and T
+    std::vector<size_t> offs(nbox + 1, 0);
+    for (int b = 0; b < nbox; b++) offs[b + 1] = offs[b] + (size_t)(ns + 1) * boxes[b].ncell;
+    Buf scratch;
+    if (scratch.grow(std::max<size_t>(8, offs[nbox] * sizeof(double)))) return fail(CHEM_E_NOMEM, "autotune scratch");
+    auto copy_all = [&](bool save) -> int {
+        for (int b = 0; b < nbox; b++) {
+            const chem_box& x = boxes[b];
+            if (!x.ncell) continue;
+            double* base = scratch.as<double>() + offs[b];
+            for (int k = 0; k < ns; k++) {
+                double* dev = x.Y + (size_t)k * x.ldY;
+                double* sc = base + (size_t)k * x.ncell;
+                HIPCHK(hipMemcpyAsync(save ? sc : dev, save ? dev : sc, x.ncell * sizeof(double),
+                                      hipMemcpyDeviceToDevice, c->stream));
+            }
+            double* scT = base + (size_t)ns * x.ncell;
+            HIPCHK(hipMemcpyAsync(save ? scT : x.T, save ? x.T : scT, x.ncell * sizeof(double),
+                                  hipMemcpyDeviceToDevice, c->stream));
+        }
+        return 0;
+    };
+    int rc = copy_all(true);
+    if (rc) return rc;
+    const Options keep = c->opt;
+    std::vector<int> groups;
+    if (c->m->ops && c->opt.precision == 0) groups.push_back(0);
+    const int n = ns + 1;
+    for (int g : {4, 8, 16, 32, 64})
+        if (g * coop_R(g) >= n && (n <= 16 ? g <= 16 : g >= 32)) groups.push_back(g);
+    struct Cand { int group, max_rounds, nstar, kmax_bulk, grid_waves; };
+    std::vector<Cand> cands;
+    for (int g : groups)
+        for (int mr : {0, 24})
+            for (int gw : {0, 2}) {
+                if (mr == 0) cands.push_back({g, 0, keep.nactive_star, keep.kmax_bulk, gw});
+                else for (int ns_ : {10000, 100000}) cands.push_back({g, mr, ns_, 5, gw});
+            }
+    std::vector<chem_box> bx(boxes, boxes + nbox);
+    double best = 1e300;
+    Cand bestc = cands[0];
+    for (const Cand& k : cands) {
+        c->opt = keep;
+        c->opt.group = k.group;
+        c->opt.max_rounds = k.max_rounds;
+        c->opt.nactive_star = k.nstar;
+        c->opt.kmax_bulk = k.kmax_bulk;
+        const int Gk = resolve_group(c, total);
+        c->opt.grid_waves = k.grid_waves == 0 ? 0 : k.grid_waves * (Gk == 0 ? 1 : coop_blocks_per_cu(c, Gk));
+        c->opt.use_graph = 0;
+        double ms = 0.0;
+        for (int rep = 0; rep < 2; rep++) {   // first run warms up (allocations, code load)
+            rc = copy_all(false);
+            if (rc) break;
+            chem_stats st;
+            rc = run(c, bx, rtol, atol, &st, false);
+            if (rc < 0) break;
+            ms = st.t_total_ms;
+        }
+        if (rc < 0) break;
+        if (ms < best) {
+            best = ms;
+            bestc = k;
+            bestc.grid_waves = c->opt.grid_waves;
+        }
+    }
+    c->opt = keep;
+    int rc2 = copy_all(false);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (rc < 0) return rc;
+    if (rc2) return rc2;
+    c->opt.group = bestc.group;
+    c->opt.max_rounds = bestc.max_rounds;
+    c->opt.nactive_star = bestc.nstar;
+    c->opt.kmax_bulk = bestc.kmax_bulk;
+    c->opt.grid_waves = bestc.grid_waves;
+    if (best_ms) *best_ms = best;
+    if (cache_path) {
+        FILE* f = fopen(cache_path, "a");
+        if (f) {
+            fprintf(f, "{\"key\": \"%s\", \"group\": %d, \"max_rounds\": %d, \"nactive_star\": %d, \"kmax_bulk\": %d, "
+                       "\"grid_waves\": %d, \"ms\": %.6f}\n",
+                    key, bestc.group, bestc.max_rounds, bestc.nstar, bestc.kmax_bulk, bestc.grid_waves, best);
+            fclose(f);
+        }
+    }
     return CHEM_OK;
 }
 
