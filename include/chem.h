@@ -95,6 +95,14 @@ typedef struct {
     double t_screen_ms, t_bulk_ms, t_sparse_ms;
     /* the part of rhs_evals .. lin_solves spent in the bulk rounds */
     int64_t bulk_rhs_evals, bulk_jac_evals, bulk_lu_facts, bulk_lin_solves;
+    /* surrogate pass: cells whose predicted increment was accepted (the
+     * cells it handed to the integrator are n_fallback) and its device time */
+    int64_t n_surrogate;
+    double t_surrogate_ms;
+    /* surrogate rejections by the first check that failed: features outside
+     * the training envelope, a mass fraction below -10 atol, temperature
+     * mismatch, one-step vs two-step disagreement */
+    int64_t surr_reject[4];
 } chem_stats;
 
 /* One AMR box (a separately allocated grid): device pointers, column-major
@@ -145,6 +153,10 @@ void chem_ctx_destroy(chem_ctx_t c);
  *                 -1 = automatic (default)
  *   use_graph     1 = capture the enqueued pipeline of chem_integrate_boxes in a
  *                 hipGraph and replay it while the box table is unchanged, default 1
+ *   surrogate     1 = run the learned surrogate on the active cells before the
+ *                 implicit integration (needs chem_load_surrogate and algorithm 1);
+ *                 cells failing its trust check are integrated, default 0
+ *   surr_rtol     relative tolerance of the surrogate's consistency check, default 1e-4
  * Returns CHEM_E_INVAL for an unknown key or out-of-range value. */
 int chem_set_option(chem_ctx_t c, const char* key, double value);
 int chem_get_option(chem_ctx_t c, const char* key, double* value);
@@ -196,7 +208,72 @@ int chem_eval_rhs(chem_ctx_t c, int64_t ncell, const double* rho, const double* 
 int chem_autotune(chem_ctx_t c, int nbox, const chem_box* boxes, double rtol, double atol,
                   const char* cache_path, double* best_ms);
 
+/* Learned surrogate of the chemistry step (an addition to the method: the
+ * paper has no learned component).  A network 12 -> 256 -> 256 -> 256 -> 10
+ * with GELU maps (T, ln(p/atm), ln max(Y_k, 1e-20) for 9 species, ln dt),
+ * z-scored, to z-scored asinh-scaled increments (dY_k / (1e-4 |Y_k| + 1e-14),
+ * dT / (1e-4 T)); inference runs in BF16 on the matrix cores with FP32
+ * accumulation.  A cell's prediction is accepted only if the features of
+ * every network evaluation lie in the training envelope, every decoded
+ * increment (projected onto element conservation) keeps each Y >= -10 atol
+ * and a temperature recovered from the fixed e within 0.5 K of the predicted
+ * one, and the one-step prediction N(y0, dt) agrees with the two-step
+ * N(N(y0, dt/2), dt/2) (a property of the exact flow) in the weighted RMS
+ * norm with weights 1/(surr_rtol |y| + atol); other cells are
+ * integrated implicitly.  Weights file (little endian): "CHEMSURR", int32
+ * version 1, nin 12, nh 256, nout 10, nspec 9, uint64 mechanism structure
+ * hash, float32 parameters (chem_mlp layout), float32 feature mean[12] and
+ * std[12], target mean[10] and std[10], float64 raw-feature envelope
+ * low[12] and high[12].  Errors: CHEM_E_INVAL (file), CHEM_E_STATE (the
+ * context's mechanism is not the compiled 9-species structure it was trained
+ * for), CHEM_E_HIP / CHEM_E_NOMEM. */
 int chem_load_surrogate(chem_ctx_t c, const char* weights_path);
+/* Training pairs of the surrogate for n cells on the device: raw features
+ * X [n][12] of (rho, Y0, T0, dt) and raw targets [n][10] (asinh-scaled
+ * increments to Y1, T1) as float32, before standardisation.  Y0, Y1 are
+ * [9][n] column major; rho, T0, T1, dt [n].  CHEM_E_STATE unless the
+ * mechanism has 9 species. */
+int chem_surrogate_pairs(chem_ctx_t c, int64_t n, const double* rho, const double* Y0, const double* T0,
+                         const double* Y1, const double* T1, const double* dt, float* X, float* targets);
+/* Structure hash of a mechanism (what surrogate files and tuning caches key on). */
+int chem_mech_hash(chem_mech_t m, uint64_t* hash);
+
+/* Network kernels (training and inference of the surrogate), on device
+ * buffers, enqueued on `stream` (a hipStream_t, NULL = default stream).
+ * Parameters are one FP32 vector of chem_mlp_nparams() = 137482 entries:
+ * W1[256][12], b1[256], W2[256][256], b2, W3[256][256], b3, W4[10][256],
+ * b4[10] (W[out][in]).  X is [batch][12] and out [batch][10], row major.
+ * ws is a caller-owned workspace of chem_mlp_workspace_floats(batch) floats;
+ * chem_mlp_forward with mode 0 (FP32) leaves there the activations that
+ * chem_mlp_backward reads; mode 1 is BF16 matrix-core inference.  Errors:
+ * CHEM_E_INVAL for NULL or out-of-range arguments, CHEM_E_HIP. */
+int64_t chem_mlp_nparams(void);
+int64_t chem_mlp_workspace_floats(int64_t batch);
+int chem_mlp_forward(void* stream, int64_t batch, const float* params, const float* X, float* out, float* ws,
+                     int mode);
+/* grads (same layout as params) of the loss whose output gradient is dout
+ * [batch][10], after a mode-0 forward of the same batch into ws. */
+int chem_mlp_backward(void* stream, int64_t batch, const float* params, const float* X, const float* ws,
+                      const float* dout, float* grads);
+/* mean squared error over n values: dout = 2 (out - target) / n; loss (device
+ * double, may be NULL) receives the mean. */
+int chem_mlp_mse(void* stream, int64_t n, const float* out, const float* target, float* dout, double* loss);
+/* Adam with bias correction, step counted from 1; m and v start at zero. */
+int chem_mlp_adam(void* stream, int64_t n, float* params, const float* grads, float* m, float* v, double lr,
+                  double beta1, double beta2, double eps, int step);
+/* Minibatch of `batch` rows drawn with replacement from X [n_data][12] and
+ * T [n_data][10] by a counter-based generator (SplitMix64 of seed, step, row). */
+int chem_mlp_gather(void* stream, int64_t n_data, const float* X, const float* T, int64_t batch, uint64_t seed,
+                    int64_t step, float* Xb, float* Tb);
+/* Column mean and standard deviation of data [n][cols] (cols <= 64); acc is
+ * a device scratch of 2 cols doubles. */
+int chem_mlp_colstats(void* stream, int64_t n, int cols, const float* data, double* acc, float* mean, float* sd);
+/* Column minimum and maximum of data [n][cols] (cols <= 64) into lo, hi
+ * (device doubles); scratch is 2 cols unsigned ints of device memory. */
+int chem_mlp_colrange(void* stream, int64_t n, int cols, const float* data, unsigned int* scratch, double* lo,
+                      double* hi);
+/* data = (data - mean) / sd, column-wise, in place. */
+int chem_mlp_standardize(void* stream, int64_t n, int cols, float* data, const float* mean, const float* sd);
 int chem_synchronize(chem_ctx_t c);
 const char* chem_last_error(void);
 

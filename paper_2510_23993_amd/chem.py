@@ -25,10 +25,13 @@ class chem_stats(C.Structure):
         "n_fallback", "steps_total", "attempts_total", "rhs_evals", "jac_evals", "lu_facts",
         "lin_solves", "max_steps_cell")] + [(n, C.c_double) for n in (
         "t_total_ms", "t_screen_ms", "t_bulk_ms", "t_sparse_ms")] + [(n, C.c_int64) for n in (
-        "bulk_rhs_evals", "bulk_jac_evals", "bulk_lu_facts", "bulk_lin_solves")]
+        "bulk_rhs_evals", "bulk_jac_evals", "bulk_lu_facts", "bulk_lin_solves")] + [
+        ("n_surrogate", C.c_int64), ("t_surrogate_ms", C.c_double), ("surr_reject", C.c_int64 * 4)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["surr_reject"] = list(d["surr_reject"])
+        return d
 
 
 class chem_box(C.Structure):
@@ -48,7 +51,10 @@ _lib = None
 EXPORTS = ["chem_load_mechanism", "chem_mech_info", "chem_species_name", "chem_free_mechanism",
            "chem_ctx_create", "chem_ctx_destroy", "chem_set_option", "chem_get_option",
            "chem_load_surrogate", "chem_integrate", "chem_integrate_boxes", "chem_prepare_state",
-           "chem_eval_rhs", "chem_synchronize", "chem_last_error", "chem_autotune"]
+           "chem_eval_rhs", "chem_synchronize", "chem_last_error", "chem_autotune",
+           "chem_mlp_nparams", "chem_mlp_workspace_floats", "chem_mlp_forward", "chem_mlp_backward",
+           "chem_mlp_mse", "chem_mlp_adam", "chem_mlp_gather", "chem_mlp_colstats", "chem_mlp_standardize",
+           "chem_mlp_colrange", "chem_surrogate_pairs", "chem_mech_hash"]
 
 
 def lib():
@@ -84,6 +90,20 @@ def lib():
     L.chem_synchronize.argtypes = [vp]
     L.chem_autotune.argtypes = [vp, C.c_int, C.POINTER(chem_box), dbl, dbl, C.c_char_p,
                                 C.POINTER(dbl)]
+    L.chem_mlp_nparams.restype = i64
+    L.chem_mlp_nparams.argtypes = []
+    L.chem_mlp_workspace_floats.restype = i64
+    L.chem_mlp_workspace_floats.argtypes = [i64]
+    L.chem_mlp_forward.argtypes = [vp, i64, vp, vp, vp, vp, C.c_int]
+    L.chem_mlp_backward.argtypes = [vp, i64, vp, vp, vp, vp, vp]
+    L.chem_mlp_mse.argtypes = [vp, i64, vp, vp, vp, vp]
+    L.chem_mlp_adam.argtypes = [vp, i64, vp, vp, vp, vp, dbl, dbl, dbl, dbl, C.c_int]
+    L.chem_mlp_gather.argtypes = [vp, i64, vp, vp, i64, C.c_uint64, i64, vp, vp]
+    L.chem_mlp_colstats.argtypes = [vp, i64, C.c_int, vp, vp, vp, vp]
+    L.chem_mlp_standardize.argtypes = [vp, i64, C.c_int, vp, vp, vp]
+    L.chem_mlp_colrange.argtypes = [vp, i64, C.c_int, vp, vp, vp, vp]
+    L.chem_surrogate_pairs.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.chem_mech_hash.argtypes = [vp, C.POINTER(C.c_uint64)]
     _lib = L
     return L
 
@@ -128,6 +148,12 @@ class Mechanism:
             nm = C.c_char_p()
             _check(lib().chem_species_name(h, k, C.byref(nm)))
             self.species.append(nm.value.decode())
+
+    @property
+    def hash(self) -> int:
+        h = C.c_uint64()
+        _check(lib().chem_mech_hash(self._h, C.byref(h)))
+        return h.value
 
     def __del__(self):
         try:
@@ -237,3 +263,74 @@ class Context:
 
     def synchronize(self):
         _check(lib().chem_synchronize(self._h))
+
+    def load_surrogate(self, path: str):
+        _check(lib().chem_load_surrogate(self._h, path.encode()))
+
+    def surrogate_pairs(self, rho, Y0, T0, Y1, T1, dt, X, targets):
+        """Raw float32 features [n][12] and targets [n][10] of increments."""
+        n = rho.shape[0]
+        _check(lib().chem_surrogate_pairs(self._h, n, _ptr(rho), _ptr(Y0), _ptr(T0), _ptr(Y1), _ptr(T1),
+                                          _ptr(dt), _ptr(X), _ptr(targets)))
+
+
+def _stream_handle(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class MLP:
+    """The surrogate network's kernels on float32 device tensors (parameters
+    in the flat layout of chem_mlp_forward)."""
+
+    NIN, NOUT = 12, 10
+
+    @staticmethod
+    def nparams() -> int:
+        return lib().chem_mlp_nparams()
+
+    @staticmethod
+    def workspace(batch, device="cuda"):
+        import torch
+        return torch.empty(int(lib().chem_mlp_workspace_floats(batch)), dtype=torch.float32, device=device)
+
+    @staticmethod
+    def forward(params, X, out, ws, mode=0, stream=None):
+        _check(lib().chem_mlp_forward(_stream_handle(stream), X.shape[0], _ptr(params), _ptr(X), _ptr(out),
+                                      _ptr(ws), int(mode)))
+
+    @staticmethod
+    def backward(params, X, ws, dout, grads, stream=None):
+        _check(lib().chem_mlp_backward(_stream_handle(stream), X.shape[0], _ptr(params), _ptr(X), _ptr(ws),
+                                       _ptr(dout), _ptr(grads)))
+
+    @staticmethod
+    def mse(out, target, dout, loss=None, stream=None):
+        _check(lib().chem_mlp_mse(_stream_handle(stream), out.numel(), _ptr(out), _ptr(target), _ptr(dout),
+                                  _ptr(loss)))
+
+    @staticmethod
+    def adam(params, grads, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        _check(lib().chem_mlp_adam(_stream_handle(stream), params.numel(), _ptr(params), _ptr(grads), _ptr(m),
+                                   _ptr(v), float(lr), float(beta1), float(beta2), float(eps), int(step)))
+
+    @staticmethod
+    def gather(X, T, batch, seed, step, Xb, Tb, stream=None):
+        _check(lib().chem_mlp_gather(_stream_handle(stream), X.shape[0], _ptr(X), _ptr(T), int(batch),
+                                     int(seed) & 0xFFFFFFFFFFFFFFFF, int(step), _ptr(Xb), _ptr(Tb)))
+
+    @staticmethod
+    def colstats(data, acc, mean, sd, stream=None):
+        _check(lib().chem_mlp_colstats(_stream_handle(stream), data.shape[0], data.shape[1], _ptr(data),
+                                       _ptr(acc), _ptr(mean), _ptr(sd)))
+
+    @staticmethod
+    def colrange(data, scratch, lo, hi, stream=None):
+        _check(lib().chem_mlp_colrange(_stream_handle(stream), data.shape[0], data.shape[1], _ptr(data),
+                                       _ptr(scratch), _ptr(lo), _ptr(hi)))
+
+    @staticmethod
+    def standardize(data, mean, sd, stream=None):
+        _check(lib().chem_mlp_standardize(_stream_handle(stream), data.shape[0], data.shape[1], _ptr(data),
+                                          _ptr(mean), _ptr(sd)))

@@ -1068,8 +1068,9 @@ __global__ void __launch_bounds__(64, 2) k_integrate_coop(CoopArgs a) {
                     else if (c == ns) B.T[i] = L.D[0][q];
                 }
                 if (l == 0) {
-                    a.st_int[g] = st;
-                    if (B.status) B.status[i] = st;
+                    const uint8_t fin = (st == ST_DONE && a.st_int[g] == ST_SURR_REJ) ? (uint8_t)ST_SURR_REJ : st;
+                    a.st_int[g] = fin;
+                    if (B.status) B.status[i] = fin;
                     if (MODE != PLAIN) a.flag[slot] = 2;
                     if (st != ST_DONE) incomplete++;
                 }

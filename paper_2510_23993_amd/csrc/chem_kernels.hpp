@@ -668,8 +668,10 @@ __global__ void __launch_bounds__(64) k_integrate(const Params<M>* __restrict__ 
 #pragma unroll
                 for (int k = 0; k < NS; k++) B.Y[k * B.ldY + i] = D[k * ld];
                 B.T[i] = D[NS * ld];
-                a.st_int[g] = st;
-                if (B.status) B.status[i] = st;
+                // a cell the surrogate handed over reports that it was integrated instead
+                const uint8_t fin = (st == ST_DONE && a.st_int[g] == ST_SURR_REJ) ? (uint8_t)ST_SURR_REJ : st;
+                a.st_int[g] = fin;
+                if (B.status) B.status[i] = fin;
                 if (MODE != PLAIN) a.flag[slot] = 2;
                 if (st != ST_DONE) incomplete++;
             } else {

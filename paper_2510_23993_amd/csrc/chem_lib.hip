@@ -16,6 +16,8 @@
 #include "chem_host_mech.hpp"
 #include "chem_coop.hpp"
 #include "chem_kernels.hpp"
+#include "chem_mlp.hpp"
+#include "chem_surrogate.hpp"
 #include "gen/mech_list.hpp"
 
 using namespace chem;
@@ -50,6 +52,8 @@ struct Options {
     int precision = 0;
     int use_graph = 1;
     int group = -1;   // lanes per cell: 0 = compiled one-lane kernel, 4..64 = cooperative, -1 = auto
+    int surrogate = 0;        // 1 = surrogate pass before the implicit integration
+    double surr_rtol = 1e-4;  // relative tolerance of the surrogate's consistency check
     bool operator==(const Options& o) const { return !memcmp(this, &o, sizeof(Options)); }
 };
 
@@ -91,6 +95,7 @@ struct MechOps {
     int (*prepare)(struct chem_ctx_s*, int64_t, const double*, const double*, const double*, int64_t, double*, double*);
     int (*eval)(struct chem_ctx_s*, int64_t, const double*, const double*, double*, double*);
     int (*lds_blocks)(int device);
+    int (*surrogate)(struct chem_ctx_s*, int64_t total, int nbox, double atol);
 };
 
 struct chem_mech_s {
@@ -114,8 +119,11 @@ struct chem_ctx_s {
     DevBox* h_boxes = nullptr;  // pinned staging of the box table
     size_t h_boxes_cap = 0;
     hipEvent_t ev_copy = nullptr, ev0 = nullptr, ev1 = nullptr;
-    hipEvent_t evp[3] = {nullptr, nullptr, nullptr};   // bulk start, bulk end, sparse start
+    hipEvent_t evp[5] = {};   // bulk start, bulk end, sparse start, surrogate start, surrogate end
     bool timing = false;                                 // record evp (eager calls with stats)
+    // surrogate: FP32 parameters, BF16 fragments, normalisation and projection tables
+    Buf s_params, s_bf, s_tab, s_X, s_out, s_ok, s_yh;
+    bool s_loaded = false;
     // graph cache for chem_integrate_boxes
     hipGraphExec_t gexec = nullptr;
     std::vector<chem_box> gkey;
@@ -282,6 +290,12 @@ int pipeline(chem_ctx_s* c, int64_t total, int nbox, double rtol, double atol) {
                        c->active.as<int>());
     hipLaunchKernelGGL(k_fill_u8, dim3(std::min<int64_t>(nb, 4096)), dim3(256), 0, s, c->flag.as<uint8_t>(),
                        std::max<int64_t>(total, 1), (uint8_t)0);
+    if (o.surrogate) {
+        mark(c, 3);
+        rc = c->m->ops->surrogate(c, total, nbox, atol);
+        if (rc) return rc;
+        mark(c, 4);
+    }
     const int rounds = std::min(o.max_rounds, RMAX);
     mark(c, 0);
     for (int r = 0; r < rounds; r++) {
@@ -530,8 +544,11 @@ int resolve_group(const chem_ctx_s* c, int64_t total) {
     return G;
 }
 
+int ensure_surr_ws(chem_ctx_s* c, int64_t total);
+
 int prepare_ws(chem_ctx_s* c, int64_t total) {
     const int G = resolve_group(c, total);
+    if (int rc = ensure_surr_ws(c, total)) return rc;
     const int64_t cells = std::max<int64_t>(total, 1);
     if (G == 0) {
         const int N = c->m->hm.ns + 1;
@@ -602,6 +619,12 @@ int pipeline_coop(chem_ctx_s* c, int G, int64_t total, int nbox, double rtol, do
                        c->active.as<int>());
     hipLaunchKernelGGL(k_fill_u8, dim3(std::min<int64_t>(nb, 4096)), dim3(256), 0, s, c->flag.as<uint8_t>(),
                        std::max<int64_t>(total, 1), (uint8_t)0);
+    if (o.surrogate) {
+        mark(c, 3);
+        rc = c->m->ops->surrogate(c, total, nbox, atol);
+        if (rc) return rc;
+        mark(c, 4);
+    }
     const int rounds = std::min(o.max_rounds, RMAX);
     mark(c, 0);
     for (int r = 0; r < rounds; r++) {
@@ -670,7 +693,59 @@ int prepare_any(chem_ctx_s* c, int64_t n, const double* T, const double* p, cons
     return 0;
 }
 
-#define CHEM_OPS(M) {M::HASH, M::NS, M::NR, M::TAG, upload_params<M>, pipeline<M>, prepare<M>, eval<M>, lds_blocks_per_cu<M>},
+int ensure_surr_ws(chem_ctx_s* c, int64_t total) {
+    if (!c->opt.surrogate) return 0;
+    const int64_t n = std::max<int64_t>(total, 1);
+    if (c->s_X.grow(3 * n * mlp::NIN * sizeof(float)) || c->s_out.grow(3 * n * mlp::NOUT * sizeof(float)) ||
+        c->s_ok.grow(n) || c->s_yh.grow(n * (SURR_NS + 1) * sizeof(double)))
+        return fail(CHEM_E_NOMEM, "surrogate workspace allocation failed");
+    return 0;
+}
+
+// Surrogate pass over the compacted active cells: features, three network
+// evaluations (dt, dt/2, dt/2 again from the half-step state), trust check.
+// Accepted cells are written and flagged finished; the others keep their
+// slot for the bulk rounds and the sparse phase.
+template <class M>
+int surrogate_pass(chem_ctx_s* c, int64_t total, int nbox, double atol) {
+    if constexpr (M::NS != SURR_NS) {
+        return fail(CHEM_E_STATE, "the surrogate network is built for 9 species");
+    } else {
+        int rc = ensure_surr_ws(c, total);
+        if (rc) return rc;
+        hipStream_t s = c->stream;
+        const Params<M>* P = (const Params<M>*)c->m->dparams;
+        const DevBox* db = c->boxes.as<DevBox>();
+        int* I = c->ints.as<int>();
+        const int* ids = c->active.as<int>();
+        const int* nact = I + I_NACT;
+        const SurrTables* tb = c->s_tab.as<SurrTables>();
+        const int64_t cap = std::max<int64_t>(total, 1);
+        float* X = c->s_X.as<float>();
+        float* O = c->s_out.as<float>();
+        uint8_t* ok = c->s_ok.as<uint8_t>();
+        const uint16_t* bf = c->s_bf.as<uint16_t>();
+        const mlp::MlpDev net{c->s_params.as<float>(), bf, bf + mlp::NW2H, bf + mlp::NW2H + mlp::NW3H};
+        const int64_t g1 = std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, (int64_t)c->ncu * 8));
+        const int64_t g2 = std::max<int64_t>(1, std::min<int64_t>((total + 63) / 64, (int64_t)c->ncu * 16));
+        hipLaunchKernelGGL((k_surr_prep<M>), dim3(g1), dim3(256), 0, s, P, tb, db, nbox, ids, nact, cap, X, ok);
+        for (int part = 0; part < 2; part++) {
+            rc = mlp::launch_infer(s, net, 0, nact, total, X + part * cap * mlp::NIN, O + part * cap * mlp::NOUT, c->ncu);
+            if (rc) return rc;
+        }
+        hipLaunchKernelGGL((k_surr_mid<M>), dim3(g2), dim3(64), 0, s, P, tb, db, nbox, ids, nact, cap, O, X,
+                           c->s_yh.as<double>(), ok, atol);
+        rc = mlp::launch_infer(s, net, 0, nact, total, X + 2 * cap * mlp::NIN, O + 2 * cap * mlp::NOUT, c->ncu);
+        if (rc) return rc;
+        hipLaunchKernelGGL((k_surr_accept<M>), dim3(g2), dim3(64), 0, s, P, tb, db, nbox, ids, nact, cap, O,
+                           c->s_yh.as<double>(), ok, c->flag.as<uint8_t>(), c->st_int.as<uint8_t>(),
+                           c->opt.surr_rtol, atol, c->ctr.as<Counters>());
+        HIPCHK(hipGetLastError());
+        return 0;
+    }
+}
+
+#define CHEM_OPS(M) {M::HASH, M::NS, M::NR, M::TAG, upload_params<M>, pipeline<M>, prepare<M>, eval<M>, lds_blocks_per_cu<M>, surrogate_pass<M>},
 const MechOps g_ops[] = {CHEM_FOR_EACH_MECH(CHEM_OPS)};
 
 int stage_boxes(chem_ctx_s* c, const std::vector<DevBox>& v) {
@@ -712,6 +787,9 @@ int finish_stats(chem_ctx_s* c, int64_t total, chem_stats* st) {
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
     memset(st, 0, sizeof(*st));
+    st->n_fallback = (int64_t)(cp[0].surr_rej + cp[1].surr_rej);
+    st->n_surrogate = (int64_t)(cp[0].surr_ok + cp[1].surr_ok);
+    for (int r = 0; r < 4; r++) st->surr_reject[r] = (int64_t)cp[0].surr_why[r];
     st->bulk_rhs_evals = (int64_t)cp[1].rhs;
     st->bulk_jac_evals = (int64_t)cp[1].jac;
     st->bulk_lu_facts = (int64_t)cp[1].lu;
@@ -724,6 +802,13 @@ int finish_stats(chem_ctx_s* c, int64_t total, chem_stats* st) {
             HIPCHK(hipEventElapsedTime(&b, c->ev0, c->evp[0]));
         } else {
             HIPCHK(hipEventElapsedTime(&b, c->ev0, c->evp[2]));
+        }
+        if (c->opt.surrogate) {
+            float sa = 0.f, sb = 0.f;
+            HIPCHK(hipEventElapsedTime(&sb, c->ev0, c->evp[3]));
+            HIPCHK(hipEventElapsedTime(&sa, c->evp[3], c->evp[4]));
+            b = sb;
+            st->t_surrogate_ms = sa;
         }
         st->t_screen_ms = b;
         st->t_bulk_ms = a;
@@ -762,6 +847,8 @@ int run(chem_ctx_s* c, const std::vector<chem_box>& bx, double rtol, double atol
         bool allow_graph) {
     if (!(rtol > 0) || !(atol >= 0) || !std::isfinite(rtol) || !std::isfinite(atol))
         return fail(CHEM_E_INVAL, "rtol must be > 0 and atol >= 0");
+    if (c->opt.surrogate && (c->opt.algorithm != 1 || !c->s_loaded))
+        return fail(CHEM_E_STATE, "the surrogate pass needs a loaded surrogate and the bulk-sparse algorithm");
     std::vector<DevBox> v;
     int64_t off = 0;
     for (const auto& b : bx) {
@@ -937,6 +1024,10 @@ int chem_set_option(chem_ctx_t c, const char* key, double v) {
     else if (k == "grid_waves" && in(0, 64)) o.grid_waves = (int)v;
     else if (k == "precision" && in(0, 1)) o.precision = (int)v;
     else if (k == "use_graph" && in(0, 1)) o.use_graph = (int)v;
+    else if (k == "surrogate" && in(0, 1)) {
+        if (v == 1 && !c->s_loaded) return fail(CHEM_E_STATE, "no surrogate loaded");
+        o.surrogate = (int)v;
+    } else if (k == "surr_rtol" && in(1e-12, 1.0)) o.surr_rtol = v;
     else if (k == "group" && (v == -1 || v == 0 || v == 4 || v == 8 || v == 16 || v == 32 || v == 64)) {
         if (v == 0 && !c->m->ops) return fail(CHEM_E_INVAL, "no compiled one-lane kernel for this mechanism");
         o.group = (int)v;
@@ -958,6 +1049,8 @@ int chem_get_option(chem_ctx_t c, const char* key, double* v) {
     else if (k == "precision") *v = o.precision;
     else if (k == "use_graph") *v = o.use_graph;
     else if (k == "group") *v = o.group;
+    else if (k == "surrogate") *v = o.surrogate;
+    else if (k == "surr_rtol") *v = o.surr_rtol;
     else return fail(CHEM_E_INVAL, "unknown option: " + k);
     return CHEM_OK;
 }
@@ -986,6 +1079,26 @@ int chem_prepare_state(chem_ctx_t c, int64_t n, const double* T, const double* p
     return prepare_any(c, n, T, p, Y, ldY, rho, e);
 }
 
+int chem_surrogate_pairs(chem_ctx_t c, int64_t n, const double* rho, const double* Y0, const double* T0,
+                         const double* Y1, const double* T1, const double* dt, float* X, float* targets) {
+    if (!c || n < 0 || (n > 0 && (!rho || !Y0 || !T0 || !Y1 || !T1 || !dt || !X || !targets)))
+        return fail(CHEM_E_INVAL, "bad arguments");
+    if (c->m->hm.ns != SURR_NS) return fail(CHEM_E_STATE, "the surrogate features are defined for 9 species");
+    if (n == 0) return 0;
+    HIPCHK(hipSetDevice(c->device));
+    const int64_t grid = std::min<int64_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_surr_pairs, dim3(grid), dim3(256), 0, c->stream, c->m->cm, n, rho, Y0, T0, Y1, T1, dt, X,
+                       targets);
+    HIPCHK(hipGetLastError());
+    return 0;
+}
+
+int chem_mech_hash(chem_mech_t m, uint64_t* hash) {
+    if (!m || !hash) return fail(CHEM_E_INVAL, "NULL argument");
+    *hash = m->hm.hash;
+    return 0;
+}
+
 int chem_eval_rhs(chem_ctx_t c, int64_t n, const double* rho, const double* y, double* f, double* J) {
     if (!c || n < 0 || (n > 0 && (!rho || !y || !f))) return fail(CHEM_E_INVAL, "bad arguments");
     HIPCHK(hipSetDevice(c->device));
@@ -993,9 +1106,65 @@ int chem_eval_rhs(chem_ctx_t c, int64_t n, const double* rho, const double* y, d
 }
 
 int chem_load_surrogate(chem_ctx_t c, const char* path) {
-    (void)c;
-    (void)path;
-    return fail(CHEM_E_STATE, "surrogate not available in this build");
+    if (!c || !path) return fail(CHEM_E_INVAL, "NULL argument");
+    const HostMech& hm = c->m->hm;
+    if (hm.ns != SURR_NS || !c->m->ops) return fail(CHEM_E_STATE, "the surrogate needs a compiled 9-species mechanism");
+    FILE* f = fopen(path, "rb");
+    if (!f) return fail(CHEM_E_INVAL, std::string("cannot open ") + path);
+    std::unique_ptr<FILE, int (*)(FILE*)> guard(f, fclose);
+    char magic[8];
+    int32_t hdr[5];
+    uint64_t hash = 0;
+    std::vector<float> params(mlp::NPARAM), norm(2 * mlp::NIN + 2 * mlp::NOUT);
+    std::vector<double> env(2 * mlp::NIN);
+    if (fread(magic, 1, 8, f) != 8 || memcmp(magic, "CHEMSURR", 8) || fread(hdr, 4, 5, f) != 5 ||
+        fread(&hash, 8, 1, f) != 1)
+        return fail(CHEM_E_INVAL, "not a surrogate weights file");
+    if (hdr[0] != 1 || hdr[1] != mlp::NIN || hdr[2] != mlp::NH || hdr[3] != mlp::NOUT || hdr[4] != SURR_NS)
+        return fail(CHEM_E_INVAL, "surrogate file version or network shape not supported");
+    if (hash != hm.hash) return fail(CHEM_E_STATE, "surrogate trained for another mechanism structure");
+    if (fread(params.data(), 4, params.size(), f) != params.size() || fread(norm.data(), 4, norm.size(), f) != norm.size() ||
+        fread(env.data(), 8, env.size(), f) != env.size())
+        return fail(CHEM_E_INVAL, "truncated surrogate file");
+    SurrTables t{};
+    for (int i = 0; i < mlp::NIN; i++) {
+        t.mean_x[i] = norm[i];
+        t.sd_x[i] = norm[mlp::NIN + i];
+        t.env_lo[i] = env[i];
+        t.env_hi[i] = env[mlp::NIN + i];
+    }
+    for (int i = 0; i < mlp::NOUT; i++) {
+        t.mean_t[i] = norm[2 * mlp::NIN + i];
+        t.sd_t[i] = norm[2 * mlp::NIN + mlp::NOUT + i];
+    }
+    for (float v : norm)
+        if (!std::isfinite(v)) return fail(CHEM_E_INVAL, "non-finite normalisation");
+    for (int i = 0; i < mlp::NIN; i++)
+        if (!(t.sd_x[i] > 0)) return fail(CHEM_E_INVAL, "non-positive feature scale");
+    t.ne = 0;
+    for (int e = 0; e < hm.ne; e++) {
+        bool used = false;
+        for (int k = 0; k < hm.ns; k++) used = used || hm.comp[k * hm.ne + e] != 0;
+        if (!used) continue;
+        if (t.ne == SURR_NEMAX) return fail(CHEM_E_STATE, "too many elements for the surrogate projection");
+        for (int k = 0; k < hm.ns; k++) t.A[t.ne][k] = hm.comp[k * hm.ne + e] / hm.W[k];
+        t.ne++;
+    }
+    HIPCHK(hipSetDevice(c->device));
+    if (c->s_params.grow(params.size() * 4) || c->s_bf.grow(mlp::NBF16 * 2) || c->s_tab.grow(sizeof(SurrTables)))
+        return fail(CHEM_E_NOMEM, "surrogate allocation failed");
+    HIPCHK(hipMemcpy(c->s_params.p, params.data(), params.size() * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->s_tab.p, &t, sizeof t, hipMemcpyHostToDevice));
+    int rc = mlp::convert_bf16(c->stream, c->s_params.as<float>(), c->s_bf.as<uint16_t>());
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (c->gexec) {
+        (void)hipGraphExecDestroy(c->gexec);
+        c->gexec = nullptr;
+        c->gkey.clear();
+    }
+    c->s_loaded = true;
+    return CHEM_OK;
 }
 
 int chem_synchronize(chem_ctx_t c) {
@@ -1143,3 +1312,7 @@ int chem_autotune(chem_ctx_t c, int nbox, const chem_box* boxes, double rtol, do
 }
 
 }  // extern "C"
+
+namespace chem {
+int set_error(int code, const char* msg) { return fail(code, msg ? msg : ""); }
+}  // namespace chem

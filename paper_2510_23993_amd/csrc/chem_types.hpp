@@ -51,6 +51,8 @@ struct DevBox {
 // Device counters (one set per context).
 struct Counters {
     unsigned long long steps, attempts, rhs, jac, lu, solves, max_attempts, incomplete;
+    unsigned long long surr_ok, surr_rej;   // surrogate pass: accepted, handed to the integrator
+    unsigned long long surr_why[4];         // first failed check: envelope, Y >= -10 atol, T, one-step vs two-step
 };
 
 }  // namespace chem

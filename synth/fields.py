@@ -263,3 +263,44 @@ def m53_base_Y(species: List[str], W: np.ndarray) -> np.ndarray:
         X[species.index(s)] = v
     w = X * W
     return w / w.sum()
+
+
+def c5_training_states(n: int, seed: int = 1005) -> Cells:
+    """Initial states for the surrogate's training pairs, drawn from the
+    distributions of the other workloads and somewhat wider: 40% burnt gas
+    near equilibrium (T 2900 K +-4%, p 18 atm +-4%, progress 0.95-1), 35%
+    shocked induction gas (T 1500-3000 K and p 40-20 atm along the band,
+    +-6% noise, progress 0.5 s^3), 25% independent reactors as in c1_cells.
+    Per-cell dt: 5e-9 s x 10^U(-0.3, 0.3) for the first two groups,
+    10^U(-9, -7) s for the reactors.  cls: 0 burnt, 1 induction, 2 reactor."""
+    rng = np.random.default_rng(seed)
+    nb, ni = int(0.40 * n), int(0.35 * n)
+    nc = n - nb - ni
+    T = np.empty(n)
+    p = np.empty(n)
+    lam = np.empty(n)
+    Z = np.full(n, Z_ST)
+    dt = np.empty(n)
+    cls = np.zeros(n, dtype=np.int8)
+    b = slice(0, nb)
+    T[b] = 2900.0 * (1 + rng.uniform(-0.04, 0.04, nb))
+    p[b] = 18.0 * ATM * (1 + rng.uniform(-0.04, 0.04, nb))
+    lam[b] = rng.uniform(0.95, 1.0, nb)
+    i = slice(nb, nb + ni)
+    s = rng.uniform(0.0, 1.0, ni)
+    T[i] = (1500.0 + 1500.0 * s) * (1 + rng.uniform(-0.06, 0.06, ni))
+    p[i] = (40.0 - 20.0 * s) * ATM * (1 + rng.uniform(-0.06, 0.06, ni))
+    lam[i] = 0.5 * s ** 3
+    cls[i] = 1
+    dt[:nb + ni] = 5e-9 * 10.0 ** rng.uniform(-0.3, 0.3, nb + ni)
+    c = slice(nb + ni, n)
+    T[c] = rng.uniform(1000.0, 2500.0, nc)
+    p[c] = rng.uniform(1.0, 20.0, nc) * ATM
+    Z[c] = Z_from_phi(rng.uniform(0.5, 2.0, nc))
+    lam[c] = rng.uniform(0.0, 1.0, nc)
+    dt[c] = 10.0 ** rng.uniform(-9.0, -7.0, nc)
+    cls[c] = 2
+    Yu = unburnt_Y(Z)
+    Ye = eq_table("m9_eq_ZTp.npz")(Z=Z, T=T, lnp=np.log(p))
+    Y = _renorm((1 - lam) * Yu + lam * Ye)
+    return Cells(T=T, p=p, Y=np.ascontiguousarray(Y), dt=dt, cls=cls)

@@ -1,0 +1,179 @@
+"""Surrogate network kernels through the C ABI against the CPU FP64
+reference: FP32 forward and backward (1e-5 of the output / gradient scale),
+BF16 matrix-core inference (2e-2), MSE, Adam, minibatch sampling, column
+statistics, and a short training run that must reduce the loss."""
+import numpy as np
+import pytest
+
+from oracle import omlp
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def chem():
+    import paper_2510_23993_amd as chem
+    return chem
+
+
+def dev(a, dtype=None):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype or torch.float32, device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+@pytest.fixture(scope="module")
+def net():
+    rng = np.random.default_rng(41)
+    p = omlp.init_params(rng)
+    B = 300                       # several 64-row tiles and a ragged tail
+    X = rng.normal(size=(B, 12))
+    T = rng.normal(size=(B, 10))
+    return p, X, T
+
+
+def _run_forward(chem, p, X, mode):
+    import torch
+    B = X.shape[0]
+    out = torch.zeros((B, 10), dtype=torch.float32, device="cuda")
+    ws = chem.MLP.workspace(B)
+    chem.MLP.forward(dev(p), dev(X), out, ws, mode=mode)
+    torch.cuda.synchronize()
+    return host(out), ws
+
+
+def test_nparams(chem):
+    assert chem.MLP.nparams() == omlp.n_params()
+
+
+def test_forward_fp32_vs_oracle(chem, net):
+    p, X, _ = net
+    out, _ = _run_forward(chem, p, X, 0)
+    ref, _ = omlp.forward(p, X)
+    err = np.max(np.abs(out - ref)) / np.max(np.abs(ref))
+    print(f"FP32 forward: max err / max |out| = {err:.2e}")
+    assert err < 1e-5
+
+
+def test_inference_bf16_mfma_vs_oracle(chem, net):
+    p, X, _ = net
+    out, _ = _run_forward(chem, p, X, 1)
+    ref, _ = omlp.forward(p, X)
+    err = np.max(np.abs(out - ref)) / np.max(np.abs(ref))
+    print(f"BF16 MFMA inference: max err / max |out| = {err:.2e}")
+    assert err < 2e-2
+    # a wrong lane layout would decorrelate the outputs entirely
+    assert np.corrcoef(out.ravel(), ref.ravel())[0, 1] > 0.999
+
+
+@pytest.mark.parametrize("B", [300, 37, 4096])
+def test_backward_vs_oracle(chem, B):
+    import torch
+    rng = np.random.default_rng(42 + B)
+    p = omlp.init_params(rng)
+    X = rng.normal(size=(B, 12))
+    T = rng.normal(size=(B, 10))
+    loss_ref, g_ref = omlp.loss_and_grad(p, X, T)
+    out = torch.zeros((B, 10), dtype=torch.float32, device="cuda")
+    ws = chem.MLP.workspace(B)
+    pd, Xd, Td = dev(p), dev(X), dev(T)
+    chem.MLP.forward(pd, Xd, out, ws, mode=0)
+    dout = torch.zeros_like(out)
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    chem.MLP.mse(out, Td, dout, loss)
+    g = torch.zeros(p.size, dtype=torch.float32, device="cuda")
+    chem.MLP.backward(pd, Xd, ws, dout, g)
+    torch.cuda.synchronize()
+    assert float(loss.item()) == pytest.approx(loss_ref, rel=1e-5)
+    gg = host(g)
+    for w, (o, i), b, n in omlp.layout():
+        for lo, hi in ((w, w + o * i), (b, b + n)):
+            sc = np.max(np.abs(g_ref[lo:hi]))
+            err = np.max(np.abs(gg[lo:hi] - g_ref[lo:hi])) / sc
+            assert err < 1e-4, (B, lo, err)
+
+
+def test_adam_vs_oracle(chem):
+    import torch
+    rng = np.random.default_rng(43)
+    n = 10007
+    p, g = rng.normal(size=n), rng.normal(size=n)
+    m, v = rng.normal(size=n) * 0.1, rng.uniform(0, 1, n)
+    pd, md, vd = dev(p), dev(m), dev(v)
+    chem.MLP.adam(pd, dev(g), md, vd, step=7, lr=1e-3)
+    torch.cuda.synchronize()
+    p1, m1, v1 = omlp.adam_step(p, g, m, v, 7, 1e-3)
+    assert np.allclose(host(pd), p1, rtol=1e-6, atol=1e-7)
+    assert np.allclose(host(md), m1, rtol=1e-6, atol=1e-7)
+    assert np.allclose(host(vd), v1, rtol=1e-6, atol=1e-7)
+
+
+def test_gather_and_column_statistics(chem):
+    import torch
+    rng = np.random.default_rng(44)
+    N = 5000
+    X = rng.normal(size=(N, 12)) * np.arange(1, 13) + np.arange(12)
+    T = rng.normal(size=(N, 10))
+    Xd, Td = dev(X), dev(T)
+    Xb = torch.zeros((512, 12), dtype=torch.float32, device="cuda")
+    Tb = torch.zeros((512, 10), dtype=torch.float32, device="cuda")
+    chem.MLP.gather(Xd, Td, 512, 99, 3, Xb, Tb)
+    Xh, Th = host(Xb), host(Tb)
+    Xf = host(Xd)
+    for r in range(512):   # every sampled row is a data row, features and targets together
+        j = np.where(np.all(Xf == Xh[r], axis=1))[0]
+        assert j.size >= 1 and np.array_equal(host(Td)[j[0]], Th[r])
+    Xb2 = torch.zeros_like(Xb)
+    chem.MLP.gather(Xd, Td, 512, 99, 3, Xb2, Tb)
+    assert torch.equal(Xb, Xb2)
+    acc = torch.zeros(24, dtype=torch.float64, device="cuda")
+    mean = torch.zeros(12, dtype=torch.float32, device="cuda")
+    sd = torch.zeros(12, dtype=torch.float32, device="cuda")
+    chem.MLP.colstats(Xd, acc, mean, sd)
+    lo = torch.zeros(12, dtype=torch.float64, device="cuda")
+    hi = torch.zeros(12, dtype=torch.float64, device="cuda")
+    scratch = torch.zeros(24, dtype=torch.int32, device="cuda")
+    chem.MLP.colrange(Xd, scratch, lo, hi)
+    torch.cuda.synchronize()
+    assert np.allclose(host(mean), Xf.mean(axis=0), rtol=1e-5, atol=1e-5)
+    assert np.allclose(host(sd), Xf.std(axis=0), rtol=1e-5)
+    assert np.array_equal(host(lo), Xf.min(axis=0)) and np.array_equal(host(hi), Xf.max(axis=0))
+    chem.MLP.standardize(Xd, mean, sd)
+    torch.cuda.synchronize()
+    Z = host(Xd)
+    assert np.allclose(Z.mean(axis=0), 0, atol=1e-4) and np.allclose(Z.std(axis=0), 1, atol=1e-4)
+
+
+def test_short_training_reduces_loss(chem):
+    """Fit a smooth synthetic map for 300 Adam steps on the GPU kernels."""
+    import torch
+    rng = np.random.default_rng(45)
+    N, B = 20000, 1024
+    X = rng.normal(size=(N, 12))
+    A = rng.normal(size=(12, 10)) / np.sqrt(12)
+    T = np.tanh(X @ A) + 0.1 * (X[:, :10] ** 2)
+    Xd, Td = dev(X), dev(T)
+    p = dev(omlp.init_params(rng))
+    m, v = torch.zeros_like(p), torch.zeros_like(p)
+    g = torch.zeros_like(p)
+    Xb = torch.zeros((B, 12), dtype=torch.float32, device="cuda")
+    Tb = torch.zeros((B, 10), dtype=torch.float32, device="cuda")
+    out = torch.zeros((B, 10), dtype=torch.float32, device="cuda")
+    dout = torch.zeros_like(out)
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ws = chem.MLP.workspace(B)
+    hist = []
+    for step in range(1, 301):
+        chem.MLP.gather(Xd, Td, B, 7, step, Xb, Tb)
+        chem.MLP.forward(p, Xb, out, ws, mode=0)
+        chem.MLP.mse(out, Tb, dout, loss)
+        chem.MLP.backward(p, Xb, ws, dout, g)
+        chem.MLP.adam(p, g, m, v, step, 1e-3)
+        if step in (1, 300):
+            torch.cuda.synchronize()
+            hist.append(float(loss.item()))
+    print(f"training loss {hist[0]:.4f} -> {hist[1]:.4f}")
+    assert hist[1] < 0.1 * hist[0]
