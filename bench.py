@@ -76,6 +76,10 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=0, help="oracle sample size (0 = the whole field)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--opt", action="append", default=[], help="key=value library option")
+    ap.add_argument("--workload", default="detonation", choices=["detonation", "amr", "m53"],
+                    help="detonation: the bench line (default); amr: 400 AMR boxes, persistent "
+                         "graph vs per-box launches; m53: 53-species mechanism, FP64 and mixed")
+    ap.add_argument("--cells", type=int, default=65536, help="m53 workload: cells")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the chemistry step "
@@ -86,6 +90,10 @@ def main():
     import torch
     import paper_2510_23993_amd as chem
     from synth import fields
+    if args.workload == "amr":
+        return bench_amr(args, torch, chem, fields)
+    if args.workload == "m53":
+        return bench_m53(args, torch, chem, fields)
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -196,6 +204,162 @@ def main():
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cells, args, n)
+    print(json.dumps(out))
+
+
+def _opts(ctx):
+    return {k: ctx.get_option(k) for k in ("t_react_min", "kmax_bulk", "nactive_star", "kmax_sparse",
+                                            "max_rounds", "grid_waves", "group", "precision")}
+
+
+def bench_amr(args, torch, chem, fields):
+    """400 seeded AMR boxes over three levels (about 6M cells, dt 4e-8 / 2e-8 /
+    1e-8 s by level), jet-in-crossflow-like field.  Times K steps of: one
+    launch per box (chem_integrate per box), one chem_integrate_boxes replayed
+    from a hipGraph with default options, and the same after chem_autotune.
+    Every step restarts from a pristine device copy (inside the timed region)."""
+    boxes = fields.c3_boxes()
+    mech = chem.Mechanism(fields.M9_PATH)
+    stream = torch.cuda.Stream()
+    ntot = 0
+    dev_boxes = []
+    with torch.cuda.stream(stream):
+        ctx0 = chem.Context(mech, stream=stream)
+        for i, b in enumerate(boxes):
+            c = fields.c3_box_state(b, box_id=i)
+            n = c.T.size
+            T0 = torch.as_tensor(c.T, device="cuda")
+            p = torch.as_tensor(c.p, device="cuda")
+            Y0 = torch.as_tensor(c.Y, device="cuda").contiguous()
+            rho = torch.empty(n, dtype=torch.float64, device="cuda")
+            e = torch.empty_like(rho)
+            ctx0.prepare_state(T0, p, Y0, rho, e)
+            dev_boxes.append(dict(rho=rho, e=e, Y=torch.empty_like(Y0), T=torch.empty_like(T0), Y0=Y0, T0=T0,
+                                  status=torch.empty(n, dtype=torch.uint8, device="cuda"), dt=b.dt,
+                                  level=b.level))
+            ntot += n
+    torch.cuda.synchronize()
+
+    def reset():
+        for d in dev_boxes:
+            d["Y"].copy_(d["Y0"])
+            d["T"].copy_(d["T0"])
+
+    def timed(fn):
+        with torch.cuda.stream(stream):
+            for _ in range(max(1, args.warmup)):
+                reset()
+                fn()
+            torch.cuda.synchronize()
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t0 = time.perf_counter()
+            ev0.record(stream)
+            for _ in range(args.steps):
+                reset()
+                fn()
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            return 1e3 * (time.perf_counter() - t0) / args.steps, ev0.elapsed_time(ev1) / args.steps
+
+    res = {}
+    with torch.cuda.stream(stream):
+        per = chem.Context(mech, stream=stream, use_graph=0)
+        res["per_box_launches"] = timed(lambda: [per.integrate(d["rho"], d["e"], d["Y"], d["T"], d["dt"], args.rtol,
+                                                               args.atol, status=d["status"], stats=False)
+                                                 for d in dev_boxes])
+        g = chem.Context(mech, stream=stream, use_graph=1)
+        res["graph_default"] = timed(lambda: g.integrate_boxes(dev_boxes, args.rtol, args.atol, stats=False))
+        tuned = chem.Context(mech, stream=stream, use_graph=1)
+        reset()
+        t0 = time.perf_counter()
+        tuned_opts, tune_ms = tuned.autotune(dev_boxes, args.rtol, args.atol)
+        t_tune = time.perf_counter() - t0
+        res["graph_autotuned"] = timed(lambda: tuned.integrate_boxes(dev_boxes, args.rtol, args.atol, stats=False))
+        # counters and phase times of one eager call with the tuned options
+        tuned.set_option("use_graph", 0)
+        reset()
+        st = tuned.integrate_boxes(dev_boxes, args.rtol, args.atol)
+    torch.cuda.synchronize()
+    wall_ms, ev_ms = res["graph_autotuned"]
+    model = mech_flop_model(fields.M9_PATH)
+    flops = algorithmic_flops(model, st)
+    bulk = {k: st["bulk_" + k] for k in ("rhs_evals", "jac_evals", "lu_facts", "lin_solves")}
+    f_bulk = algorithmic_flops(model, bulk)
+    if st["t_bulk_ms"] >= st["t_sparse_ms"]:
+        kern, f_k, t_k = "bulk-round integration kernel", f_bulk, st["t_bulk_ms"]
+    else:
+        kern, f_k, t_k = "sparse-phase integration kernel", flops - f_bulk, st["t_sparse_ms"]
+    achieved = f_k / (t_k * 1e-3) / 1e12
+    out = {
+        "metric": METRIC, "value": ntot / (wall_ms * 1e-3), "unit": "cell-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall_ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"AMR batching: 400 boxes over 3 levels ({ntot} cells), jet-in-crossflow-like "
+                               "field, dt 4e-8/2e-8/1e-8 s by level, 9-species mechanism",
+                   "rtol": args.rtol, "atol": args.atol, "tuned_options": tuned_opts,
+                   "autotune_s": t_tune, "autotune_best_call_ms": tune_ms},
+        "event_ms_per_step": ev_ms,
+        "variants_ms_per_step": {k: {"wall": v[0], "events": v[1]} for k, v in res.items()},
+        "speedup_graph_autotuned_vs_per_box": res["per_box_launches"][0] / wall_ms,
+        "stats": {k: st[k] for k in ("n_active0", "n_active_after_bulk", "n_bulk_rounds", "steps_total",
+                                     "attempts_total", "t_total_ms", "t_screen_ms", "t_bulk_ms", "t_sparse_ms")},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None, "kernel": kern,
+                     "kernel_ms_per_call": t_k, "flops_per_call": f_k},
+    }
+    print(json.dumps(out))
+
+
+def bench_m53(args, torch, chem, fields):
+    """53-species / 325-reaction mechanism, n cells of the seeded T/p/progress
+    distribution, dt 1e-7 s.  FP64 at rtol 1e-7 / atol 1e-20 (the loosest
+    tolerance at which the FP64 oracle meets 1e-4 relative on species above
+    1e-10), cooperative schedules of 32 and 64 lanes per cell, and the
+    FP32-exponential mode at rtol 1e-6 for context (it does not reach the
+    budget on this mechanism)."""
+    mech = chem.Mechanism(fields.M53_PATH)
+    cells = fields.c4_cells(args.cells, seed=1004)
+    n = cells.T.size
+    T0 = torch.as_tensor(cells.T, device="cuda")
+    p = torch.as_tensor(cells.p, device="cuda")
+    Y0 = torch.as_tensor(cells.Y, device="cuda").contiguous()
+    ctx0 = chem.Context(mech)
+    rho = torch.empty(n, dtype=torch.float64, device="cuda")
+    e = torch.empty_like(rho)
+    ctx0.prepare_state(T0, p, Y0, rho, e)
+    Y, T = torch.empty_like(Y0), torch.empty_like(T0)
+    status = torch.empty(n, dtype=torch.uint8, device="cuda")
+    runs = {}
+    for name, opts, rtol in (("fp64_g64", dict(group=64), 1e-7), ("fp64_g32", dict(group=32), 1e-7),
+                             ("mixed_g64_rtol1e-6", dict(group=64, precision=1, kmax_sparse=20000), 1e-6),
+                             ("fp64_g64_rtol1e-6", dict(group=64), 1e-6)):
+        ctx = chem.Context(mech, **opts)
+        Y.copy_(Y0)
+        T.copy_(T0)
+        st = ctx.integrate(rho, e, Y, T, cells.dt, rtol, 1e-20, status=status)
+        runs[name] = {"ms": st["t_total_ms"], "rtol": rtol, "steps_total": st["steps_total"],
+                      "max_steps_cell": st["max_steps_cell"],
+                      "status_counts": np.bincount(status.cpu().numpy(), minlength=8).tolist(),
+                      "cell_steps_per_s": n / (st["t_total_ms"] * 1e-3)}
+        print(json.dumps({name: runs[name]}), file=sys.stderr, flush=True)
+    best = min(("fp64_g64", "fp64_g32"), key=lambda k: runs[k]["ms"])
+    out = {"metric": METRIC, "value": runs[best]["cell_steps_per_s"], "unit": "cell-steps/s", "n_gpus": 1,
+           "steps": 1, "warmup": 0, "ms_per_step": runs[best]["ms"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"53-species/325-reaction synthetic mechanism, {n} cells, dt 1e-7 s",
+                      "rtol": 1e-7, "atol": 1e-20, "schedule": best},
+           "variants": runs}
+    if not args.no_cpu:
+        import oracle
+        orc = oracle.Oracle(fields.M53_PATH)
+        m = 256
+        r, ee = orc.state_from_TPY(cells.T[:m], cells.p[:m], cells.Y[:, :m])
+        threads = len(os.sched_getaffinity(0))
+        t0 = time.perf_counter()
+        orc.integrate(r, ee, cells.Y[:, :m], cells.dt, 1e-7, 1e-20, T=cells.T[:m], nthreads=threads)
+        wall = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": m / wall, "unit": "cell-steps/s", "cores": threads, "kind": "oracle",
+                               "sample": f"the first {m} cells, rtol 1e-7 / atol 1e-20, {wall:.2f} s wall"}
     print(json.dumps(out))
 
 

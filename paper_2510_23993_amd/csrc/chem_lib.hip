@@ -116,9 +116,14 @@ struct chem_ctx_s {
     // workspace
     Buf st_int, active, sparse, flag, bcnt, boff, ints, ctr, save, laneD, boxes;
     int64_t cap_cells = 0, cap_lanes = 0;
-    DevBox* h_boxes = nullptr;  // pinned staging of the box table
-    size_t h_boxes_cap = 0;
-    hipEvent_t ev_copy = nullptr, ev0 = nullptr, ev1 = nullptr;
+    // pinned staging ring of the box table: a call only waits for the upload
+    // issued NSTAGE calls earlier, so back-to-back calls keep the host ahead
+    static constexpr int NSTAGE = 8;
+    DevBox* h_boxes[NSTAGE] = {};
+    size_t h_cap[NSTAGE] = {};
+    hipEvent_t ev_copy[NSTAGE] = {};
+    int stage = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipEvent_t evp[5] = {};   // bulk start, bulk end, sparse start, surrogate start, surrogate end
     bool timing = false;                                 // record evp (eager calls with stats)
     // surrogate: FP32 parameters, BF16 fragments, normalisation and projection tables
@@ -751,20 +756,18 @@ const MechOps g_ops[] = {CHEM_FOR_EACH_MECH(CHEM_OPS)};
 int stage_boxes(chem_ctx_s* c, const std::vector<DevBox>& v) {
     const size_t bytes = v.size() * sizeof(DevBox);
     if (c->boxes.grow(bytes)) return fail(CHEM_E_NOMEM, "box table allocation failed");
-    if (bytes > c->h_boxes_cap) {
-        if (c->h_boxes) {
-            HIPCHK(hipEventSynchronize(c->ev_copy));
-            HIPCHK(hipHostFree(c->h_boxes));
-        }
-        c->h_boxes = nullptr;
-        HIPCHK(hipHostMalloc((void**)&c->h_boxes, bytes));
-        c->h_boxes_cap = bytes;
-    } else {
-        HIPCHK(hipEventSynchronize(c->ev_copy));  // previous upload finished reading the staging buffer
+    const int k = c->stage = (c->stage + 1) % chem_ctx_s::NSTAGE;
+    HIPCHK(hipEventSynchronize(c->ev_copy[k]));   // the upload that last read this slot is done
+    if (bytes > c->h_cap[k]) {
+        if (c->h_boxes[k]) HIPCHK(hipHostFree(c->h_boxes[k]));
+        c->h_boxes[k] = nullptr;
+        c->h_cap[k] = 0;
+        HIPCHK(hipHostMalloc((void**)&c->h_boxes[k], bytes));
+        c->h_cap[k] = bytes;
     }
-    memcpy(c->h_boxes, v.data(), bytes);
-    HIPCHK(hipMemcpyAsync(c->boxes.p, c->h_boxes, bytes, hipMemcpyHostToDevice, c->stream));
-    HIPCHK(hipEventRecord(c->ev_copy, c->stream));
+    memcpy(c->h_boxes[k], v.data(), bytes);
+    HIPCHK(hipMemcpyAsync(c->boxes.p, c->h_boxes[k], bytes, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipEventRecord(c->ev_copy[k], c->stream));
     return 0;
 }
 
@@ -988,11 +991,13 @@ int chem_ctx_create(chem_mech_t m, int device, void* stream, chem_ctx_t* out) {
     hipDeviceProp_t prop;
     HIPCHK(hipGetDeviceProperties(&prop, device));
     c->ncu = prop.multiProcessorCount;
-    HIPCHK(hipEventCreateWithFlags(&c->ev_copy, hipEventDisableTiming));
+    for (auto& e : c->ev_copy) {
+        HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        HIPCHK(hipEventRecord(e, c->stream));
+    }
     HIPCHK(hipEventCreate(&c->ev0));
     HIPCHK(hipEventCreate(&c->ev1));
     for (auto& e : c->evp) HIPCHK(hipEventCreate(&e));
-    HIPCHK(hipEventRecord(c->ev_copy, c->stream));
     *out = c.release();
     return CHEM_OK;
 }
@@ -1001,8 +1006,10 @@ void chem_ctx_destroy(chem_ctx_t c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
-    if (c->h_boxes) (void)hipHostFree(c->h_boxes);
-    if (c->ev_copy) (void)hipEventDestroy(c->ev_copy);
+    for (int k = 0; k < chem_ctx_s::NSTAGE; k++) {
+        if (c->h_boxes[k]) (void)hipHostFree(c->h_boxes[k]);
+        if (c->ev_copy[k]) (void)hipEventDestroy(c->ev_copy[k]);
+    }
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     for (auto e : c->evp)
