@@ -621,9 +621,11 @@ __global__ void __launch_bounds__(64) k_integrate(const Params<M>* __restrict__ 
             L.round_att = 0;
             if (MODE != PLAIN && a.flag[slot] == 1) {
                 const SaveArea& S = a.sv;
-#pragma unroll
+                // copies are only partly unrolled: a full unroll keeps every
+                // element in flight at once and spills the integrator state
+#pragma unroll 4
                 for (int r = 0; r < ND * N; r++) D[r * ld] = S.D[r * S.ld + slot];
-#pragma unroll
+#pragma unroll 4
                 for (int r = 0; r < N * N; r++) A[r * 64] = S.LU[r * S.ld + slot];
 #pragma unroll
                 for (int r = 0; r < N; r++) L.piv[r] = S.piv[r * S.ld + slot];
@@ -676,9 +678,9 @@ __global__ void __launch_bounds__(64) k_integrate(const Params<M>* __restrict__ 
                 if (st != ST_DONE) incomplete++;
             } else {
                 const SaveArea& S = a.sv;
-#pragma unroll
+#pragma unroll 4
                 for (int rr = 0; rr < ND * N; rr++) S.D[rr * S.ld + slot] = D[rr * ld];
-#pragma unroll
+#pragma unroll 4
                 for (int rr = 0; rr < N * N; rr++) S.LU[rr * S.ld + slot] = A[rr * 64];
 #pragma unroll
                 for (int rr = 0; rr < N; rr++) S.piv[rr * S.ld + slot] = (int8_t)L.piv[rr];
