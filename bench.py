@@ -27,6 +27,45 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "chemistry cell-steps/s, plain FP64 vs batched/mixed/surrogate at fixed error"
 
 
+# HBM traffic of the bulk-round kernel per call, from two rocprofv3 --pmc
+# passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch summed over the 24
+# launches of one call) on the detonation patch with the options below.  The
+# counters are scaled by what they read for a device copy of known size
+# (151 MB: FETCH_SIZE reads half, WRITE_SIZE reads it exactly).  Valid only
+# for the kernel sources they were taken on (hash below) and these options.
+TRAFFIC_PMC = {
+    "src_sha1": "6642f5181175a7fc2e702f734a7022e767bcf5dd",
+    "options": {"group": 0.0, "max_rounds": 24.0, "nactive_star": 100000.0, "kmax_bulk": 20.0},
+    "fetch_kib": 478433 + 2653600 + 2514520 + 21 * 20, "fetch_factor": 2.0,
+    "write_kib": 3142260 + 5648060 + 4551410, "write_factor": 1.0,
+}
+
+
+def kernel_sources_sha1():
+    import glob
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2510_23993_amd", "csrc")
+    files = sorted(glob.glob(os.path.join(csrc, "*.hpp")) + glob.glob(os.path.join(csrc, "*.hip"))
+                   + [os.path.join(csrc, "gen_mech.py"), os.path.join(ROOT, "synth", "data", "m9.mech")])
+    h = hashlib.sha1()
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(options, kernel):
+    """Bytes per call of the bulk-round kernel, or None when the sources, the
+    options or the dominant kernel differ from the ones measured."""
+    t = TRAFFIC_PMC
+    if not kernel.startswith("bulk-round") or kernel_sources_sha1() != t["src_sha1"]:
+        return None
+    if any(options.get(k) != v for k, v in t["options"].items()):
+        return None
+    return 1024.0 * (t["fetch_kib"] * t["fetch_factor"] + t["write_kib"] * t["write_factor"])
+
+
 def mech_flop_model(path):
     """Algorithmic FLOPs per RHS / Jacobian / LU / solve, counted from the
     mechanism's nonzeros (exp, log and divide count as one FLOP)."""
@@ -80,6 +119,7 @@ def main():
                     help="detonation: the bench line (default); amr: 400 AMR boxes, persistent "
                          "graph vs per-box launches; m53: 53-species mechanism, FP64 and mixed")
     ap.add_argument("--cells", type=int, default=65536, help="m53 workload: cells")
+    ap.add_argument("--no-tune", action="store_true", help="detonation workload: skip chem_autotune")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the chemistry step "
@@ -121,6 +161,17 @@ def main():
         T.copy_(T_d)
         return ctx.integrate(rho, e, Y, T, cells.dt, args.rtol, args.atol, status=status, stats=stats)
 
+    # schedule chosen by the library's autotuner on this field (outside the
+    # timed region, reported separately)
+    tune = None
+    if not args.no_tune and not args.opt:
+        Y.copy_(Y0)
+        T.copy_(T_d)
+        t0 = time.perf_counter()
+        opts, best_ms = ctx.autotune([dict(rho=rho, e=e, Y=Y, T=T, status=status, dt=cells.dt)],
+                                     args.rtol, args.atol)
+        tune = {"options": opts, "best_call_ms": best_ms, "seconds": time.perf_counter() - t0}
+
     # warmup (also yields the per-call counters used for the FLOP count)
     st = None
     for _ in range(max(1, args.warmup)):
@@ -153,6 +204,8 @@ def main():
     group = ctx.get_option("group")
     sched = ("one lane per cell" if (group == 0 or (group < 0 and n >= 65536)) else
              f"{int(group) if group > 0 else 16} lanes per cell")
+    if ctx.get_option("algorithm") == 1 and ctx.get_option("max_rounds") == 0:
+        sched += ", no bulk rounds"
     if st["t_bulk_ms"] >= st["t_sparse_ms"]:
         kern, f_k, t_k = f"bulk-round integration kernel ({sched})", f_bulk, st["t_bulk_ms"]
     else:
@@ -184,12 +237,16 @@ def main():
                        "t_react_min", "kmax_bulk", "nactive_star", "kmax_sparse", "max_rounds",
                        "grid_waves", "group")}},
         "event_ms_per_step": ev_ms,
+        "autotune": tune,
         "stats": {k: st[k] for k in ("n_active0", "n_active_after_bulk", "n_bulk_rounds",
                                      "steps_total", "attempts_total", "rhs_evals", "jac_evals",
                                      "lu_facts", "lin_solves", "max_steps_cell", "t_total_ms")},
         "status_counts": np.bincount(status_h, minlength=8).tolist(),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+                     "traffic": measured_traffic({k: ctx.get_option(k) for k in TRAFFIC_PMC["options"]}, kern),
+                     "traffic_unit": "bytes per call (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
+                     "algorithmic_bytes_per_call": 8 * (2 * mech.ns + 4) * st["n_active0"],
                      "kernel": kern, "kernel_ms_per_call": t_k, "flops_per_call": f_k,
                      "whole_call": {"flops": flops, "ms": st["t_total_ms"],
                                     "tflops": flops / (st["t_total_ms"] * 1e-3) / 1e12},

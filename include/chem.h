@@ -198,7 +198,7 @@ int chem_eval_rhs(chem_ctx_t c, int64_t ncell, const double* rho, const double* 
                   double* J);
 
 /* Autotuner: times candidate schedules (lanes per cell, bulk phase on/off,
- * N*, persistent grid size) on the given boxes and sets the fastest as the
+ * N*, steps per bulk round, persistent grid size) on the given boxes and sets the fastest as the
  * context's options.  Y and T of every box are restored afterwards (the call
  * synchronises the stream).  The choice is cached as a JSON line keyed by
  * (GPU arch, mechanism structure hash, box count, cell count, rtol, atol,

@@ -1261,11 +1261,16 @@ int chem_autotune(chem_ctx_t c, int nbox, const chem_box* boxes, double rtol, do
         if (g * coop_R(g) >= n && (n <= 16 ? g <= 16 : g >= 32)) groups.push_back(g);
     struct Cand { int group, max_rounds, nstar, kmax_bulk, grid_waves; };
     std::vector<Cand> cands;
+    // grid_waves 2 (two waves' worth of workgroups per CU) only for the
+    // cooperative schedules: the one-lane kernel's LDS already limits it
     for (int g : groups)
         for (int mr : {0, 24})
             for (int gw : {0, 2}) {
+                if (g == 0 && gw) continue;
                 if (mr == 0) cands.push_back({g, 0, keep.nactive_star, keep.kmax_bulk, gw});
-                else for (int ns_ : {10000, 100000}) cands.push_back({g, mr, ns_, 5, gw});
+                else
+                    for (int ns_ : {10000, 100000})
+                        for (int kb : {5, 20}) cands.push_back({g, mr, ns_, kb, gw});
             }
     std::vector<chem_box> bx(boxes, boxes + nbox);
     double best = 1e300;
