@@ -145,9 +145,11 @@ void chem_ctx_destroy(chem_ctx_t c);
  *   kmax_sparse   step limit of the sparse phase / plain path, default 1e5
  *   max_rounds    bulk-round launches enqueued per call (device decides how many run), default 24
  *   grid_waves    waves per CU of the persistent integration kernel, default 0 (auto)
- *   precision     0 = FP64 rates (default); 1 = exp/log of the rate evaluation on the
- *                 FP32 units with FP64 range reduction (Newton, LU, T inversion,
- *                 contractions and net rates stay FP64)
+ *   precision     0 = FP64 rates (default); 1 = the exponentials of the rate evaluation
+ *                 (and the falloff logarithms) on the FP32 units with FP64 range
+ *                 reduction; ln C, the contractions, near-equilibrium net rates
+ *                 (-q_f expm1 of the FP64 log ratio), Newton, LU and the T inversion
+ *                 stay FP64.  Available on every schedule
  *   group         lanes per cell: 0 = compiled one-lane kernel (if the mechanism's
  *                 structure was compiled in), 4/8/16/32/64 = cooperative kernels,
  *                 -1 = automatic (default)

@@ -84,24 +84,8 @@ __device__ __forceinline__ double rsel(const double* a, int s) {
 // Transcendentals of the rate evaluation.  prec = 1 uses the FP32 hardware
 // units (v_exp_f32 / v_log_f32) on a range-reduced argument and keeps the
 // range and the reduction in FP64: relative error ~1e-7 instead of ~1e-16.
-__device__ __forceinline__ double rexp(double x, int prec) {
-    if (prec == 0) return exp(x);
-    const double t = x * 1.4426950408889634074;   // log2(e)
-    const double n = rint(t);
-    const float f = (float)(t - n);                // |f| <= 1/2
-    return ldexp((double)exp2f(f), (int)fmax(fmin(n, 2000.0), -2000.0));
-}
-// e^d - 1 for |d| < 0.35 (Taylor series to d^7; truncation below 2e-8 relative)
-__device__ __forceinline__ double expm1_small(double d) {
-    return d * (1.0 + d * (1.0 / 2 + d * (1.0 / 6 + d * (1.0 / 24 + d * (1.0 / 120 + d * (1.0 / 720 + d * (1.0 / 5040)))))));
-}
-
-__device__ __forceinline__ double rlog(double c, int prec) {   // c > 0
-    if (prec == 0) return log(c);
-    int e;
-    const double m = frexp(c, &e);                 // c = m 2^e, m in [0.5, 1)
-    return ((double)log2f((float)m) + (double)e) * 0.69314718055994530942;
-}
+__device__ __forceinline__ double rexp(double x, int prec) { return prec ? exp32(x) : exp(x); }
+__device__ __forceinline__ double rlog(double c, int prec) { return prec ? log32(c) : log(c); }   // c > 0
 
 // ------------------------------------------------------------------ thermo
 __device__ __forceinline__ void coop_thermo(const double* sp, double T, double lnT, double invT,

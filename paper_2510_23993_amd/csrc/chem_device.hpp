@@ -9,9 +9,29 @@
 
 #include <cstdint>
 
+#include "chem_math.hpp"
 #include "chem_types.hpp"
 
 namespace chem {
+
+// Mechanism type with the mixed-precision rate evaluation: the same structure
+// and parameter layout, exponentials of the rates on the FP32 units.
+template <class B>
+struct MixedOf : B {
+    static constexpr int PREC = 1;
+};
+
+template <class M>
+__device__ __forceinline__ double mexp(double x) {
+    if constexpr (M::PREC) return exp32(x);
+    else return exp(x);
+}
+
+template <class M>
+__device__ __forceinline__ double mlog(double x) {
+    if constexpr (M::PREC) return log32(x);
+    else return log(x);
+}
 
 // ---------------------------------------------------------------- thermo
 // NASA-7 with pre-divided coefficients (host packs them):
@@ -136,20 +156,20 @@ __device__ __forceinline__ void rxn_k(const Params<M>& P, double lnT, double inv
     if (TY == RX_FO) {
         const double lnk0 = P.lnA0[j] + P.b0[j] * lnT - P.Ea0R[j] * invT;
         const double dlnk0 = (P.b0[j] + P.Ea0R[j] * invT) * invT;
-        const double Pr = fmax(exp(lnk0 - lnkinf) * r.M, 1e-300);
-        const double lnPr = log(Pr);
+        const double Pr = fmax(mexp<M>(lnk0 - lnkinf) * r.M, 1e-300);
+        const double lnPr = mlog<M>(Pr);
         double lnF = 0.0, dlnF_dlnPr = 0.0, dlnF_dT = 0.0;
         if (M::TROE[j] > 0) {
             const double a = P.troe[j][0], T = 1.0 / invT;
-            const double e3 = exp(-T / P.troe[j][1]), e1 = exp(-T / P.troe[j][2]);
+            const double e3 = mexp<M>(-T / P.troe[j][1]), e1 = mexp<M>(-T / P.troe[j][2]);
             double Fc = (1.0 - a) * e3 + a * e1;
             double dFc = -(1.0 - a) / P.troe[j][1] * e3 - a / P.troe[j][2] * e1;
             if (M::TROE[j] == 4) {
-                const double e2 = exp(-P.troe[j][3] * invT);
+                const double e2 = mexp<M>(-P.troe[j][3] * invT);
                 Fc += e2;
                 dFc += P.troe[j][3] * invT * invT * e2;
             }
-            const double phi = log(Fc) * INV_LN10;
+            const double phi = mlog<M>(Fc) * INV_LN10;
             const double c = -0.4 - 0.67 * phi, nn = 0.75 - 1.27 * phi;
             const double u = lnPr * INV_LN10 + c;
             const double den = nn - 0.14 * u;
@@ -166,7 +186,7 @@ __device__ __forceinline__ void rxn_k(const Params<M>& P, double lnT, double inv
             }
         }
         const double ip = 1.0 / (1.0 + Pr);
-        r.lnkf = lnkinf + lnPr + log(ip) + lnF;   // ln(kinf Pr/(1+Pr) F)
+        r.lnkf = lnkinf + lnPr + mlog<M>(ip) + lnF;   // ln(kinf Pr/(1+Pr) F)
         if (want_deriv) {
             const double dlnPr_dT = dlnk0 - dlnkinf;
             r.dlnkf_dlnM = ip + dlnF_dlnPr;
@@ -241,8 +261,21 @@ __device__ __forceinline__ void rhs_loop(const Params<M>& P, const CellEval<M>& 
         rxn_k<M, j>(P, E.lnT, E.invT, E.C, r, false);
         double lnqf, lnqr, sf, sr;
         rxn_lnq<M, j>(E, r.lnkf, lnqf, lnqr, sf, sr);
-        double q = sf * exp(lnqf);
-        if (M::REV[j]) q -= sr * exp(lnqr);
+        double q;
+        if constexpr (M::PREC) {
+            // FP32 exponentials: near equilibrium the net rate is -qf expm1(d)
+            // with the FP64 log ratio d, not a difference of two rounded q's
+            const double Ef = exp32(lnqf);
+            q = sf * Ef;
+            if (M::REV[j]) {
+                const double d = lnqr - lnqf;
+                if (sf == sr && fabs(d) < 0.35) q = -q * expm1_small(d);
+                else q -= sr * exp32(lnqr);
+            }
+        } else {
+            q = sf * exp(lnqf);
+            if (M::REV[j]) q -= sr * exp(lnqr);
+        }
         if (M::TYPE[j] == RX_TB) q *= r.M;
 #pragma unroll
         for (int i = 0; i < M::NRE[j]; i++) om[M::RSP[j][i]] -= M::RNU[j][i] * q;
@@ -293,8 +326,8 @@ __device__ __forceinline__ void jac_loop(const Params<M>& P, const CellEval<M>& 
         rxn_k<M, j>(P, E.lnT, E.invT, E.C, r, true);
         double lnqf, lnqr, sf, sr;
         rxn_lnq<M, j>(E, r.lnkf, lnqf, lnqr, sf, sr);
-        const double qf = sf * exp(lnqf);
-        const double qr = M::REV[j] ? sr * exp(lnqr) : 0.0;
+        const double qf = sf * mexp<M>(lnqf);
+        const double qr = M::REV[j] ? sr * mexp<M>(lnqr) : 0.0;
         const double mul = (TY == RX_TB) ? r.M : 1.0;
         const double net = qf - qr;
         // d ln qf/dT = dlnkf, d ln qr/dT = dlnkf - dlnKc

@@ -249,8 +249,9 @@ void mark(chem_ctx_s* c, int i) {
     if (c->timing) (void)hipEventRecord(c->evp[i], c->stream);
 }
 
-template <class M>
-int pipeline(chem_ctx_s* c, int64_t total, int nbox, double rtol, double atol) {
+// K: the kernels' mechanism type (M, or MixedOf<M> for FP32 exponentials)
+template <class M, class K>
+int pipeline_k(chem_ctx_s* c, int64_t total, int nbox, double rtol, double atol) {
     constexpr int N = M::N;
     const Options& o = c->opt;
     hipStream_t s = c->stream;
@@ -259,6 +260,7 @@ int pipeline(chem_ctx_s* c, int64_t total, int nbox, double rtol, double atol) {
                        sizeof(double) * ND * N);
     if (rc) return rc;
     const Params<M>* P = (const Params<M>*)c->m->dparams;
+    const Params<K>* PK = (const Params<K>*)c->m->dparams;   // same layout
     const DevBox* db = c->boxes.as<DevBox>();
     int* I = c->ints.as<int>();
     Counters* ctr = c->ctr.as<Counters>();
@@ -287,7 +289,7 @@ int pipeline(chem_ctx_s* c, int64_t total, int nbox, double rtol, double atol) {
         a.n_items_host = total;
         a.kmax = o.kmax_sparse;
         mark(c, 2);
-        hipLaunchKernelGGL((k_integrate<M, PLAIN>), dim3((total + 63) / 64), dim3(64), 0, s, P, a);
+        hipLaunchKernelGGL((k_integrate<K, PLAIN>), dim3((total + 63) / 64), dim3(64), 0, s, PK, a);
         return 0;
     }
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, c->bcnt.as<int>(), (int)nb, c->boff.as<int>(), I + I_NACT);
@@ -310,7 +312,7 @@ int pipeline(chem_ctx_s* c, int64_t total, int nbox, double rtol, double atol) {
         b.unfinished = I + I_UNF + r;
         b.gate = r == 0 ? I + I_NACT : I + I_UNF + r - 1;
         b.kmax = o.kmax_bulk;
-        hipLaunchKernelGGL((k_integrate<M, BULK>), dim3(grid), dim3(64), 0, s, P, b);
+        hipLaunchKernelGGL((k_integrate<K, BULK>), dim3(grid), dim3(64), 0, s, PK, b);
     }
     mark(c, 1);
     hipLaunchKernelGGL(k_count_unfinished, dim3(nb), dim3(256), 0, s, c->flag.as<uint8_t>(), I + I_NACT,
@@ -324,8 +326,14 @@ int pipeline(chem_ctx_s* c, int64_t total, int nbox, double rtol, double atol) {
     sp.queue = I + I_Q + RMAX;
     sp.kmax = o.kmax_sparse;
     mark(c, 2);
-    hipLaunchKernelGGL((k_integrate<M, SPARSE>), dim3(grid), dim3(64), 0, s, P, sp);
+    hipLaunchKernelGGL((k_integrate<K, SPARSE>), dim3(grid), dim3(64), 0, s, PK, sp);
     return 0;
+}
+
+template <class M>
+int pipeline(chem_ctx_s* c, int64_t total, int nbox, double rtol, double atol) {
+    if (c->opt.precision) return pipeline_k<M, MixedOf<M>>(c, total, nbox, rtol, atol);
+    return pipeline_k<M, M>(c, total, nbox, rtol, atol);
 }
 
 template <class M>
@@ -341,8 +349,12 @@ int prepare(chem_ctx_s* c, int64_t n, const double* T, const double* p, const do
 template <class M>
 int eval(chem_ctx_s* c, int64_t n, const double* rho, const double* y, double* f, double* J) {
     if (n == 0) return 0;
-    hipLaunchKernelGGL((k_eval_rhs<M>), dim3((n + 63) / 64), dim3(64), 0, c->stream,
-                       (const Params<M>*)c->m->dparams, n, rho, y, f, J);
+    if (c->opt.precision)
+        hipLaunchKernelGGL((k_eval_rhs<MixedOf<M>>), dim3((n + 63) / 64), dim3(64), 0, c->stream,
+                           (const Params<MixedOf<M>>*)c->m->dparams, n, rho, y, f, J);
+    else
+        hipLaunchKernelGGL((k_eval_rhs<M>), dim3((n + 63) / 64), dim3(64), 0, c->stream,
+                           (const Params<M>*)c->m->dparams, n, rho, y, f, J);
     HIPCHK(hipGetLastError());
     return 0;
 }
@@ -543,8 +555,8 @@ int resolve_group(const chem_ctx_s* c, int64_t total) {
     const int n = c->m->hm.ns + 1;
     const int coop = (n <= 16) ? 16 : 64;
     int G = c->opt.group;
-    if (G < 0) G = (c->m->ops && c->opt.precision == 0 && total >= ONE_LANE_MIN_CELLS) ? 0 : coop;
-    if (G == 0 && (!c->m->ops || c->opt.precision != 0)) G = coop;
+    if (G < 0) G = (c->m->ops && total >= ONE_LANE_MIN_CELLS) ? 0 : coop;
+    if (G == 0 && !c->m->ops) G = coop;
     if (G > 0 && G * coop_R(G) < n) G = 64;
     return G;
 }
@@ -1255,7 +1267,7 @@ int chem_autotune(chem_ctx_t c, int nbox, const chem_box* boxes, double rtol, do
     if (rc) return rc;
     const Options keep = c->opt;
     std::vector<int> groups;
-    if (c->m->ops && c->opt.precision == 0) groups.push_back(0);
+    if (c->m->ops) groups.push_back(0);
     const int n = ns + 1;
     for (int g : {4, 8, 16, 32, 64})
         if (g * coop_R(g) >= n && (n <= 16 ? g <= 16 : g >= 32)) groups.push_back(g);
