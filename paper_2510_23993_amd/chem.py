@@ -217,13 +217,7 @@ class Context:
     def integrate_boxes(self, boxes: Sequence[dict], rtol, atol, stats=True):
         """boxes: dicts with rho, e, Y ([ns, n]), T, dt and optional mask,
         status, level."""
-        arr = (chem_box * len(boxes))()
-        for i, b in enumerate(boxes):
-            n = b["rho"].shape[0]
-            _check_f64("Y", b["Y"], (self.mech.ns, n))
-            arr[i] = chem_box(n, _ptr(b["rho"]), _ptr(b["e"]), _ptr(b["Y"]), n, _ptr(b["T"]),
-                              _ptr(b.get("mask")), _ptr(b.get("status")), float(b["dt"]),
-                              int(b.get("level", 0)))
+        arr = self._box_array(boxes)
         st = chem_stats() if stats else None
         rc = _check(lib().chem_integrate_boxes(self._h, len(boxes), arr, float(rtol), float(atol),
                                                C.byref(st) if st is not None else None))
@@ -237,6 +231,8 @@ class Context:
         arr = (chem_box * len(boxes))()
         for i, b in enumerate(boxes):
             n = b["rho"].shape[0]
+            for k in ("rho", "e", "T"):
+                _check_f64(k, b[k], (n,))
             _check_f64("Y", b["Y"], (self.mech.ns, n))
             arr[i] = chem_box(n, _ptr(b["rho"]), _ptr(b["e"]), _ptr(b["Y"]), n, _ptr(b["T"]),
                               _ptr(b.get("mask")), _ptr(b.get("status")), float(b["dt"]),

@@ -422,37 +422,54 @@ __device__ __forceinline__ void jac_eval(const Params<M>& P, double rho, const d
     put(NS, NS, -dS * irho / cvs - fT * dcvs / cvs);
 }
 
-// Newton matrix A = I - c J written to LDS (element (r, c) at A[(r*N + c)*64]).
+// Lanes of a 64-lane workgroup that carry a cell.  Each carries its NN x NN
+// Newton matrix in LDS; the register file allows 4 such waves per CU, so the
+// workgroup uses fewer than 64 lanes when that lets a fourth one fit in the
+// CU's 160 KB (9 x 9 FP64 per lane: 63 lanes; 10 x 10: 51).
+template <class M>
+constexpr int lanes_per_wave() {
+    constexpr int per_lane = M::NN * M::NN * 8;
+    constexpr int lw = (160 * 1024 / 4) / per_lane;
+    return lw >= 64 ? 64 : lw;
+}
+
+// Newton matrix A = I - c J over the Newton system (species that react, then
+// T; inert species are left out) written to LDS: element (r, c) at
+// A[(r*NN + c)*LW].
 template <class M>
 __device__ __forceinline__ void newton_matrix(const Params<M>& P, double rho, const double* y,
                                               double c, double* A) {
-    constexpr int N = M::N, NS = M::NS;
+    constexpr int NN = M::NN, LW = lanes_per_wave<M>();
 #pragma unroll
-    for (int r = 0; r < NS; r++)
+    for (int r = 0; r < NN - 1; r++)
 #pragma unroll
-        for (int q = 0; q < NS; q++) A[(r * N + q) * 64] = (r == q) ? 1.0 : 0.0;
-    auto acc = [&](int i, int j, double v) { A[(i * N + j) * 64] -= c * v; };
+        for (int q = 0; q < NN - 1; q++) A[(r * NN + q) * LW] = (r == q) ? 1.0 : 0.0;
+    auto acc = [&](int i, int j, double v) {
+        const int si = M::SYS[i], sj = M::SYS[j];
+        if (si >= 0 && sj >= 0) A[(si * NN + sj) * LW] -= c * v;
+    };
     jac_eval<M>(P, rho, y, acc, [&](int i, int j, double v) {
-        A[(i * N + j) * 64] = (i == j ? 1.0 : 0.0) - c * v;
+        const int si = M::SYS[i], sj = M::SYS[j];
+        if (si >= 0 && sj >= 0) A[(si * NN + sj) * LW] = (si == sj ? 1.0 : 0.0) - c * v;
     });
 }
 
 // --------------------------------------------------------------- dense LU
 // In-place LU with partial pivoting of the lane's N x N matrix in LDS
-// (element (r, c) at A[(r*N + c)*64]).  The diagonal is replaced by its
+// (element (r, c) at A[(r*N + c)*LW]).  The diagonal is replaced by its
 // reciprocal; pivot rows go to piv[].  Rows are swapped only from column k
 // on, and solves replay the same sequence of interchanges.  Returns false
 // if a pivot is zero or not finite.
-template <int N>
+template <int N, int LW>
 __device__ __forceinline__ bool lu_factor(double* A, int* piv) {
     bool ok = true;
 #pragma unroll
     for (int k = 0; k < N; k++) {
         int p = k;
-        double best = fabs(A[(k * N + k) * 64]);
+        double best = fabs(A[(k * N + k) * LW]);
 #pragma unroll
         for (int i = k + 1; i < N; i++) {
-            const double v = fabs(A[(i * N + k) * 64]);
+            const double v = fabs(A[(i * N + k) * LW]);
             if (v > best) {
                 best = v;
                 p = i;
@@ -463,28 +480,28 @@ __device__ __forceinline__ bool lu_factor(double* A, int* piv) {
         if (p != k) {
 #pragma unroll
             for (int c = k; c < N; c++) {
-                const double t = A[(k * N + c) * 64];
-                A[(k * N + c) * 64] = A[(p * N + c) * 64];
-                A[(p * N + c) * 64] = t;
+                const double t = A[(k * N + c) * LW];
+                A[(k * N + c) * LW] = A[(p * N + c) * LW];
+                A[(p * N + c) * LW] = t;
             }
         }
         double rowk[N];
 #pragma unroll
-        for (int c = k; c < N; c++) rowk[c] = A[(k * N + c) * 64];
+        for (int c = k; c < N; c++) rowk[c] = A[(k * N + c) * LW];
         const double inv = 1.0 / rowk[k];
-        A[(k * N + k) * 64] = inv;
+        A[(k * N + k) * LW] = inv;
 #pragma unroll
         for (int i = k + 1; i < N; i++) {
-            const double l = A[(i * N + k) * 64] * inv;
-            A[(i * N + k) * 64] = l;
+            const double l = A[(i * N + k) * LW] * inv;
+            A[(i * N + k) * LW] = l;
 #pragma unroll
-            for (int c = k + 1; c < N; c++) A[(i * N + c) * 64] -= l * rowk[c];
+            for (int c = k + 1; c < N; c++) A[(i * N + c) * LW] -= l * rowk[c];
         }
     }
     return ok;
 }
 
-template <int N>
+template <int N, int LW>
 __device__ __forceinline__ void lu_solve(const double* A, const int* piv, double* b) {
 #pragma unroll
     for (int k = 0; k < N; k++) {
@@ -499,14 +516,14 @@ __device__ __forceinline__ void lu_solve(const double* A, const int* piv, double
         }
         const double bk = b[k];
 #pragma unroll
-        for (int i = k + 1; i < N; i++) b[i] -= A[(i * N + k) * 64] * bk;
+        for (int i = k + 1; i < N; i++) b[i] -= A[(i * N + k) * LW] * bk;
     }
 #pragma unroll
     for (int i = N - 1; i >= 0; i--) {
         double s = b[i];
 #pragma unroll
-        for (int c = i + 1; c < N; c++) s -= A[(i * N + c) * 64] * b[c];
-        b[i] = s * A[(i * N + i) * 64];
+        for (int c = i + 1; c < N; c++) s -= A[(i * N + c) * LW] * b[c];
+        b[i] = s * A[(i * N + i) * LW];
     }
 }
 

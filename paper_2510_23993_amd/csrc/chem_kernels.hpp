@@ -244,7 +244,7 @@ struct Lane {
     double t, tend, h, c_lu, rho;
     int k, neq, att, round_att;
     bool lu_ok, jac_fresh;
-    int piv[N];
+    int piv[M::NN];
     // per-lane statistics
     unsigned long long n_steps, n_att, n_rhs, n_jac, n_lu, n_solve;
 };
@@ -346,7 +346,7 @@ __device__ __forceinline__ int bdf_attempt(const Params<M>& P, Lane<M>& L, doubl
         L.n_jac++;
         L.n_lu++;
         L.jac_fresh = true;
-        L.lu_ok = lu_factor<N>(A, L.piv);
+        L.lu_ok = lu_factor<M::NN, lanes_per_wave<M>()>(A, L.piv);
         L.c_lu = c;
         if (!L.lu_ok) {   // singular even with a fresh Jacobian: shrink the step
             rescale<N>(D, ld, k, 0.25);
@@ -375,7 +375,14 @@ __device__ __forceinline__ int bdf_attempt(const Params<M>& P, Lane<M>& L, doubl
             fin = fin && isfinite(f[i]);
         }
         if (!fin) break;
-        lu_solve<N>(A, L.piv, f);
+        {   // solve on the Newton system; inert components keep the residual (identity rows)
+            double fs[M::NN];
+#pragma unroll
+            for (int s = 0; s < M::NN; s++) fs[s] = f[M::ISYS[s]];
+            lu_solve<M::NN, lanes_per_wave<M>()>(A, L.piv, fs);
+#pragma unroll
+            for (int s = 0; s < M::NN; s++) f[M::ISYS[s]] = fs[s];
+        }
         L.n_solve++;
         const double dn = wrms<N>(f, isc);
         const double rate = dn_old > 0.0 ? dn / dn_old : -1.0;
@@ -551,10 +558,11 @@ struct IntArgs {
 template <class M, int MODE>
 __global__ void __launch_bounds__(64) k_integrate(const Params<M>* __restrict__ Pp, IntArgs a) {
     constexpr int N = M::N, NS = M::NS;
-    __shared__ double lds[N * N * 64];
+    constexpr int NN = M::NN, LW = lanes_per_wave<M>();
+    __shared__ double lds[NN * NN * LW];
     const Params<M>& P = *Pp;
     const int lane = threadIdx.x;
-    double* A = lds + lane;
+    double* A = lds + lane;   // lanes >= LW carry no cell and never touch it
     if (MODE == BULK) {
         const int nact = *a.n_items_dev;
         if (nact == 0) return;
@@ -573,7 +581,7 @@ __global__ void __launch_bounds__(64) k_integrate(const Params<M>* __restrict__ 
     int slot = -1;
     int64_t g = -1;
     int bidx = 0;
-    bool exhausted = false;
+    bool exhausted = lane >= LW;
     bool static_taken = false;
 
     for (;;) {
@@ -581,8 +589,8 @@ __global__ void __launch_bounds__(64) k_integrate(const Params<M>* __restrict__ 
         if (MODE == PLAIN) {
             if (cur < 0 && !static_taken) {
                 static_taken = true;
-                const int64_t it = lslot;
-                if (it < n_items && a.st_int[it] == ST_ACTIVE) cur = it;
+                const int64_t it = blockIdx.x * (int64_t)LW + lane;   // LW cells per workgroup
+                if (lane < LW && it < n_items && a.st_int[it] == ST_ACTIVE) cur = it;
             }
         } else {
             for (;;) {
@@ -626,9 +634,9 @@ __global__ void __launch_bounds__(64) k_integrate(const Params<M>* __restrict__ 
 #pragma unroll 4
                 for (int r = 0; r < ND * N; r++) D[r * ld] = S.D[r * S.ld + slot];
 #pragma unroll 4
-                for (int r = 0; r < N * N; r++) A[r * 64] = S.LU[r * S.ld + slot];
+                for (int r = 0; r < NN * NN; r++) A[r * LW] = S.LU[r * S.ld + slot];
 #pragma unroll
-                for (int r = 0; r < N; r++) L.piv[r] = S.piv[r * S.ld + slot];
+                for (int r = 0; r < NN; r++) L.piv[r] = S.piv[r * S.ld + slot];
                 L.t = S.scal[0 * S.ld + slot];
                 L.h = S.scal[1 * S.ld + slot];
                 L.c_lu = S.scal[2 * S.ld + slot];
@@ -681,9 +689,9 @@ __global__ void __launch_bounds__(64) k_integrate(const Params<M>* __restrict__ 
 #pragma unroll 4
                 for (int rr = 0; rr < ND * N; rr++) S.D[rr * S.ld + slot] = D[rr * ld];
 #pragma unroll 4
-                for (int rr = 0; rr < N * N; rr++) S.LU[rr * S.ld + slot] = A[rr * 64];
+                for (int rr = 0; rr < NN * NN; rr++) S.LU[rr * S.ld + slot] = A[rr * LW];
 #pragma unroll
-                for (int rr = 0; rr < N; rr++) S.piv[rr * S.ld + slot] = (int8_t)L.piv[rr];
+                for (int rr = 0; rr < NN; rr++) S.piv[rr * S.ld + slot] = (int8_t)L.piv[rr];
                 S.scal[0 * S.ld + slot] = L.t;
                 S.scal[1 * S.ld + slot] = L.h;
                 S.scal[2 * S.ld + slot] = L.c_lu;

@@ -95,6 +95,7 @@ struct MechOps {
     int (*prepare)(struct chem_ctx_s*, int64_t, const double*, const double*, const double*, int64_t, double*, double*);
     int (*eval)(struct chem_ctx_s*, int64_t, const double*, const double*, double*, double*);
     int (*lds_blocks)(int device);
+    int lanes_per_wave;   // one-lane kernels: cells per 64-lane workgroup
     int (*surrogate)(struct chem_ctx_s*, int64_t total, int nbox, double atol);
 };
 
@@ -241,7 +242,9 @@ int64_t persistent_grid(chem_ctx_s* c) {
 }
 
 int64_t lanes_needed(chem_ctx_s* c, int64_t total) {
-    return std::max<int64_t>(persistent_grid(c) * 64, c->opt.algorithm == 0 ? ((total + 63) / 64) * 64 : 0);
+    // the plain path launches one workgroup per lanes_per_wave cells
+    const int lw = c->m->ops ? c->m->ops->lanes_per_wave : 64;
+    return std::max<int64_t>(persistent_grid(c) * 64, c->opt.algorithm == 0 ? ((total + lw - 1) / lw) * 64 : 0);
 }
 
 // phase boundary event (eager calls that return statistics only)
@@ -289,7 +292,8 @@ int pipeline_k(chem_ctx_s* c, int64_t total, int nbox, double rtol, double atol)
         a.n_items_host = total;
         a.kmax = o.kmax_sparse;
         mark(c, 2);
-        hipLaunchKernelGGL((k_integrate<K, PLAIN>), dim3((total + 63) / 64), dim3(64), 0, s, PK, a);
+        constexpr int LW = lanes_per_wave<K>();
+        hipLaunchKernelGGL((k_integrate<K, PLAIN>), dim3((total + LW - 1) / LW), dim3(64), 0, s, PK, a);
         return 0;
     }
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, c->bcnt.as<int>(), (int)nb, c->boff.as<int>(), I + I_NACT);
@@ -762,7 +766,7 @@ int surrogate_pass(chem_ctx_s* c, int64_t total, int nbox, double atol) {
     }
 }
 
-#define CHEM_OPS(M) {M::HASH, M::NS, M::NR, M::TAG, upload_params<M>, pipeline<M>, prepare<M>, eval<M>, lds_blocks_per_cu<M>, surrogate_pass<M>},
+#define CHEM_OPS(M) {M::HASH, M::NS, M::NR, M::TAG, upload_params<M>, pipeline<M>, prepare<M>, eval<M>, lds_blocks_per_cu<M>, lanes_per_wave<M>(), surrogate_pass<M>},
 const MechOps g_ops[] = {CHEM_FOR_EACH_MECH(CHEM_OPS)};
 
 int stage_boxes(chem_ctx_s* c, const std::vector<DevBox>& v) {
