@@ -34,10 +34,10 @@ METRIC = "chemistry cell-steps/s, plain FP64 vs batched/mixed/surrogate at fixed
 # (151 MB: FETCH_SIZE reads half, WRITE_SIZE reads it exactly).  Valid only
 # for the kernel sources they were taken on (hash below) and these options.
 TRAFFIC_PMC = {
-    "src_sha1": "6642f5181175a7fc2e702f734a7022e767bcf5dd",
+    "src_sha1": "c8c1ebf6d52099053260e2abb30b5f15af255a8e",
     "options": {"group": 0.0, "max_rounds": 24.0, "nactive_star": 100000.0, "kmax_bulk": 20.0},
-    "fetch_kib": 478433 + 2653600 + 2514520 + 21 * 20, "fetch_factor": 2.0,
-    "write_kib": 3142260 + 5648060 + 4551410, "write_factor": 1.0,
+    "fetch_kib": 1424440 + 3744610 + 3318880 + 21 * 16.5, "fetch_factor": 2.0,
+    "write_kib": 3731030 + 6036850 + 4730940, "write_factor": 1.0,
 }
 
 
