@@ -309,11 +309,11 @@ __device__ __forceinline__ void coop_rhs(const CoopMech& M, const GL& gl, int l,
     lds_fence();   // the LDS area is reused by the next phase
 }
 
-// Newton matrix rows A = I - c J of the group's cell (own rows in registers).
-// jb: this lane's LDS row buffer, element (s, col) at jb[(s*NC + col)*64].
+// Newton matrix rows A = I - c J of the group's cell, left in this lane's LDS
+// row buffer jb: element (s, col) of the lane's own rows at jb[(s*NC + col)*64].
 template <int G, int R>
 __device__ __forceinline__ void coop_newton_matrix(const CoopMech& M, const GL& gl, int l, int base, double rho,
-                                   const double* y, double c, double (*A)[G * R], double* jb) {
+                                   const double* y, double c, double* jb) {
     constexpr int NC = G * R;
     const int ns = M.ns;
     const double T = group_T<G, R>(y, ns, base);
@@ -375,7 +375,9 @@ __device__ __forceinline__ void coop_newton_matrix(const CoopMech& M, const GL& 
     const double fT = -S * irho / cvs;
     // temperature row needs dS_m = sum_k u_k d omega_k/dC_m = W_m sum_k u_k J[k][m] / W_k,
     // reduced over the group column by column while the own rows are assembled
-#pragma unroll
+    // rolled: an unrolled loop over 64 columns (each with a group reduction)
+    // makes the kernel larger than the instruction cache
+#pragma unroll 1
     for (int col = 0; col < NC; col++) {
         double v = 0.0;
 #pragma unroll
@@ -399,33 +401,34 @@ __device__ __forceinline__ void coop_newton_matrix(const CoopMech& M, const GL& 
                     J = -E * irho / cvs - fT * dcvs / cvs;
                 }
             }
-            A[s][col] = ((k == col) ? 1.0 : 0.0) - c * J;
+            jb[(s * NC + col) * 64] = ((k == col) ? 1.0 : 0.0) - c * J;   // the Newton matrix, in place
         }
     }
     lds_fence();
 }
 
-// LU with implicit partial pivoting of the group's matrix (own rows in
-// registers).  After the call: pstep[s] = elimination step at which own row
-// became pivot; gl.perm[k] = pivot row of step k; the pivot row stores
-// 1/pivot on its diagonal and U to its right, other rows keep their
-// multipliers in the columns of the steps that eliminated them.
+// LU with implicit partial pivoting of the group's matrix (own rows in the
+// lanes' LDS row buffers A, element (s, col) at A[(s*NC + col)*64]).  After
+// the call: pstep[s] = elimination step at which own row became pivot;
+// gl.perm[k] = pivot row of step k; the pivot row stores 1/pivot on its
+// diagonal and U to its right, other rows keep their multipliers in the
+// columns of the steps that eliminated them.  Loops over steps and columns
+// run to n (not unrolled), which keeps the kernel within the instruction cache.
 template <int G, int R>
-__device__ __forceinline__ bool coop_lu(const GL& gl, int l, int n, double (*A)[G * R], int* pstep) {
+__device__ __forceinline__ bool coop_lu(const GL& gl, int l, int n, double* A, int* pstep) {
     constexpr int NC = G * R;
     bool ok = true;
 #pragma unroll
     for (int s = 0; s < R; s++) pstep[s] = -1;
-#pragma unroll
-    for (int k = 0; k < NC; k++) {
-        if (k < n) {   // uniform guard; no early exit, so the loop stays fully unrolled
+#pragma unroll 1
+    for (int k = 0; k < n; k++) {
         double best = -1.0;
         int bidx = 1 << 30;
 #pragma unroll
         for (int s = 0; s < R; s++) {
             const int i = l + G * s;
             if (i < n && pstep[s] < 0) {
-                const double v = fabs(A[s][k]);
+                const double v = fabs(A[(s * NC + k) * 64]);
                 if (v > best) {
                     best = v;
                     bidx = i;
@@ -438,13 +441,8 @@ __device__ __forceinline__ bool coop_lu(const GL& gl, int l, int n, double (*A)[
         const bool own = (p % G) == l;
         const int sp = p / G;
         if (own) {
-#pragma unroll
-            for (int col = k; col < NC; col++) {
-                double v = A[0][col];
-#pragma unroll
-                for (int q = 1; q < R; q++) v = (sp == q) ? A[q][col] : v;
-                gl.prow[col] = v;
-            }
+#pragma unroll 4
+            for (int col = k; col < n; col++) gl.prow[col] = A[(sp * NC + col) * 64];
         }
         lds_fence();
         const double inv = 1.0 / gl.prow[k];
@@ -453,17 +451,16 @@ __device__ __forceinline__ bool coop_lu(const GL& gl, int l, int n, double (*A)[
             const int i = l + G * s;
             if (own && s == sp) {
                 pstep[s] = k;
-                A[s][k] = inv;
+                A[(s * NC + k) * 64] = inv;
             } else if (i < n && pstep[s] < 0) {
-                const double m = A[s][k] * inv;
-                A[s][k] = m;
-#pragma unroll
-                for (int col = k + 1; col < NC; col++) A[s][col] -= m * gl.prow[col];
+                const double m = A[(s * NC + k) * 64] * inv;
+                A[(s * NC + k) * 64] = m;
+#pragma unroll 4
+                for (int col = k + 1; col < n; col++) A[(s * NC + col) * 64] -= m * gl.prow[col];
             }
         }
         if (l == 0) gl.perm[k] = p;
         lds_fence();
-        }
     }
     return ok;
 }
@@ -472,37 +469,33 @@ __device__ __forceinline__ bool coop_lu(const GL& gl, int l, int n, double (*A)[
 // components).  Forward: step k eliminates the broadcast pivot value from the
 // rows that became pivots later; back: column-oriented substitution.
 template <int G, int R>
-__device__ __forceinline__ void coop_solve(const GL& gl, int l, int base, int n, const double (*A)[G * R],
-                           const int* pstep, double* b) {
+__device__ __forceinline__ void coop_solve(const GL& gl, int l, int base, int n, const double* A, const int* pstep,
+                                           double* b) {
     constexpr int NC = G * R;
+#pragma unroll 1
+    for (int k = 0; k < n; k++) {
+        const int p = gl.perm[k];
+        const double z = __shfl(rsel<R>(b, p / G), base + p % G);
 #pragma unroll
-    for (int k = 0; k < NC; k++) {
-        if (k < n) {
-            const int p = gl.perm[k];
-            const double z = __shfl(rsel<R>(b, p / G), base + p % G);
-#pragma unroll
-            for (int s = 0; s < R; s++)
-                if (pstep[s] > k) b[s] -= A[s][k] * z;
-        }
+        for (int s = 0; s < R; s++)
+            if (pstep[s] > k) b[s] -= A[(s * NC + k) * 64] * z;
     }
     double x[R];
 #pragma unroll
     for (int s = 0; s < R; s++) x[s] = 0.0;
+#pragma unroll 1
+    for (int k = n - 1; k >= 0; k--) {
+        const int p = gl.perm[k];
+        // the owner of row p holds b_p (fully reduced) and 1/pivot on (sp, k)
+        double cand = 0.0;
 #pragma unroll
-    for (int k = NC - 1; k >= 0; k--) {
-        if (k < n) {
-            const int p = gl.perm[k];
-            // the owner of row p holds b_p (fully reduced) and 1/pivot on A[sp][k]
-            double cand = 0.0;
+        for (int s = 0; s < R; s++)
+            if (pstep[s] == k) cand = b[s] * A[(s * NC + k) * 64];
+        const double xk = __shfl(cand, base + p % G);
 #pragma unroll
-            for (int s = 0; s < R; s++)
-                if (pstep[s] == k) cand = b[s] * A[s][k];
-            const double xk = __shfl(cand, base + p % G);
-#pragma unroll
-            for (int s = 0; s < R; s++) {
-                if (pstep[s] >= 0 && pstep[s] < k) b[s] -= A[s][k] * xk;
-                if (l + G * s == k) x[s] = xk;
-            }
+        for (int s = 0; s < R; s++) {
+            if (pstep[s] >= 0 && pstep[s] < k) b[s] -= A[(s * NC + k) * 64] * xk;
+            if (l + G * s == k) x[s] = xk;
         }
     }
 #pragma unroll
@@ -514,8 +507,7 @@ template <int G, int R>
 struct CLane {
     static constexpr int NC = G * R;
     double D[ND][R];
-    double A[R][NC];
-    int pstep[R];
+    int pstep[R];   // the matrix rows live in the lane's LDS row buffer
     double t, tend, h, c_lu, rho;
     int k, neq, att, round_att;
     bool lu_ok, jac_fresh;
@@ -623,11 +615,11 @@ __device__ __forceinline__ int cbdf_attempt(const CoopMech& M, const GL& gl, int
     }
     const double c = L.h / gk;
     if (!L.lu_ok || fabs(c - L.c_lu) > 0.3 * L.c_lu) {
-        coop_newton_matrix<G, R>(M, gl, l, base, L.rho, yp, c, L.A, jb);
+        coop_newton_matrix<G, R>(M, gl, l, base, L.rho, yp, c, jb);
         L.n_jac++;
         L.n_lu++;
         L.jac_fresh = true;
-        L.lu_ok = coop_lu<G, R>(gl, l, n, L.A, L.pstep);
+        L.lu_ok = coop_lu<G, R>(gl, l, n, jb, L.pstep);
         L.c_lu = c;
         if (!L.lu_ok) {
             crescale<G, R>(L, k, 0.25);
@@ -658,7 +650,7 @@ __device__ __forceinline__ int cbdf_attempt(const CoopMech& M, const GL& gl, int
 #pragma unroll
         for (int o = G / 2; o >= 1; o >>= 1) fin &= __shfl_xor(fin, o);
         if (!fin) break;
-        coop_solve<G, R>(gl, l, base, n, L.A, L.pstep, f);
+        coop_solve<G, R>(gl, l, base, n, jb, L.pstep, f);
         L.n_solve++;
         const double dn = cwrms<G, R>(f, isc, n);
         const double rate = dn_old > 0.0 ? dn / dn_old : -1.0;
@@ -1001,8 +993,8 @@ __global__ void __launch_bounds__(64, 2) k_integrate_coop(CoopArgs a) {
                     const int c = l + G * q;
 #pragma unroll
                     for (int j = 0; j < ND; j++) L.D[j][q] = S.D[(j * NC + c) * S.ld + slot];
-#pragma unroll
-                    for (int col = 0; col < NC; col++) L.A[q][col] = S.A[(c * NC + col) * S.ld + slot];
+#pragma unroll 4
+                    for (int col = 0; col < NC; col++) jb[(q * NC + col) * 64] = S.A[(c * NC + col) * S.ld + slot];
                     L.pstep[q] = S.ints[c * S.ld + slot];
                     if (L.pstep[q] >= 0) gl.perm[L.pstep[q]] = c;
                 }
@@ -1065,8 +1057,8 @@ __global__ void __launch_bounds__(64, 2) k_integrate_coop(CoopArgs a) {
                     const int c = l + G * q;
 #pragma unroll
                     for (int j = 0; j < ND; j++) S.D[(j * NC + c) * S.ld + slot] = L.D[j][q];
-#pragma unroll
-                    for (int col = 0; col < NC; col++) S.A[(c * NC + col) * S.ld + slot] = L.A[q][col];
+#pragma unroll 4
+                    for (int col = 0; col < NC; col++) S.A[(c * NC + col) * S.ld + slot] = jb[(q * NC + col) * 64];
                     S.ints[c * S.ld + slot] = L.pstep[q];
                 }
                 if (l == 0) {
@@ -1139,16 +1131,14 @@ __global__ void __launch_bounds__(64) k_eval_coop(CoopMech M, int gl_stride, int
         if (i < n) f[i * ncell + c] = ff[q];
     }
     if (J) {
-        double A[R][NC];
-        // c = -1 gives A = I + J
-        coop_newton_matrix<G, R>(M, gl, l, base, rho[c], yy, -1.0, A, jb);
+        // c = -1 gives A = I + J in the row buffer
+        coop_newton_matrix<G, R>(M, gl, l, base, rho[c], yy, -1.0, jb);
 #pragma unroll
         for (int q = 0; q < R; q++) {
             const int i = l + G * q;
             if (i < n) {
-#pragma unroll
-                for (int col = 0; col < NC; col++)
-                    if (col < n) J[(i * n + col) * ncell + c] = A[q][col] - (i == col ? 1.0 : 0.0);
+                for (int col = 0; col < n; col++)
+                    J[(i * n + col) * ncell + c] = jb[(q * NC + col) * 64] - (i == col ? 1.0 : 0.0);
             }
         }
     }
