@@ -49,24 +49,63 @@ enum { RI_TYPE = 0, RI_REV, RI_TROEN, RI_DNU, RI_NRE, RI_NPR, RI_RSP, RI_RNU = R
 // LDS doubles of one group, for nsp species slots, nr reactions, nc columns
 __host__ __device__ inline int group_lds_doubles(int nsp, int nr, int nc) { return 6 * nsp + 5 * nr + 2 * nc + 8; }
 
-template <int G>
+// Partner exchange for the group reductions, combining level o = 1, 2, 4, ...
+// bottom-up: DPP within 16-lane rows (quad permutes for o = 1, 2; half-row and
+// row mirrors for o = 4, 8, which pair the already reduced quads and halves),
+// a swizzle for o = 16 and a permute across the wave halves for o = 32.  Each
+// pair of partners combines the same two values, so every lane of a group
+// ends with bit-identical results.
+template <int O>
+__device__ __forceinline__ int xchg32(int v) {
+    if constexpr (O == 1) return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
+    else if constexpr (O == 2) return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);   // quad_perm 2,3,0,1
+    else if constexpr (O == 4) return __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+    else if constexpr (O == 8) return __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false);  // row_mirror
+    else if constexpr (O == 16) return __builtin_amdgcn_ds_swizzle(v, 0x401F);                  // lane ^ 16
+    else return __shfl_xor(v, 32);
+}
+
+template <int O>
+__device__ __forceinline__ double xchg(double v) {
+    const int lo = xchg32<O>(__double2loint(v));
+    const int hi = xchg32<O>(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
+template <int G, int O = 1>
 __device__ __forceinline__ double gsum(double v) {
-#pragma unroll
-    for (int o = G / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o);
-    return v;
+    if constexpr (O < G) {
+        v += xchg<O>(v);
+        return gsum<G, 2 * O>(v);
+    } else {
+        return v;
+    }
 }
 
 // group argmax of (value, index): larger value wins, ties -> smaller index
-template <int G>
+template <int G, int O = 1>
 __device__ __forceinline__ void gargmax(double& v, int& idx) {
-#pragma unroll
-    for (int o = G / 2; o >= 1; o >>= 1) {
-        const double v2 = __shfl_xor(v, o);
-        const int i2 = __shfl_xor(idx, o);
+    if constexpr (O < G) {
+        const double v2 = xchg<O>(v);
+        const int i2 = xchg32<O>(idx);
         if (v2 > v || (v2 == v && i2 < idx)) {
             v = v2;
             idx = i2;
         }
+        gargmax<G, 2 * O>(v, idx);
+    }
+}
+
+// value of lane `src` of the group (src: lane index in the wave)
+template <int G>
+__device__ __forceinline__ double gbcast(double v, int src) {
+    if constexpr (G == 64) {   // one group per wave: src is wave-uniform
+        const int s = __builtin_amdgcn_readfirstlane(src);
+        const int lo = __builtin_amdgcn_readlane(__double2loint(v), s);
+        const int hi = __builtin_amdgcn_readlane(__double2hiint(v), s);
+        return __hiloint2double(hi, lo);
+    } else {
+        return __shfl(v, src);
     }
 }
 
@@ -275,7 +314,7 @@ __device__ __forceinline__ void coop_reactions(const CoopMech& M, const GL& gl, 
 
 template <int G, int R>
 __device__ __forceinline__ double group_T(const double* y, int ns, int base) {
-    return __shfl(rsel<R>(y, ns / G), base + ns % G);
+    return gbcast<G>(rsel<R>(y, ns / G), base + ns % G);
 }
 
 // f = dy/dt of the group's cell, distributed like y.
@@ -475,7 +514,7 @@ __device__ __forceinline__ void coop_solve(const GL& gl, int l, int base, int n,
 #pragma unroll 1
     for (int k = 0; k < n; k++) {
         const int p = gl.perm[k];
-        const double z = __shfl(rsel<R>(b, p / G), base + p % G);
+        const double z = gbcast<G>(rsel<R>(b, p / G), base + p % G);
 #pragma unroll
         for (int s = 0; s < R; s++)
             if (pstep[s] > k) b[s] -= A[(s * NC + k) * 64] * z;
@@ -491,7 +530,7 @@ __device__ __forceinline__ void coop_solve(const GL& gl, int l, int base, int n,
 #pragma unroll
         for (int s = 0; s < R; s++)
             if (pstep[s] == k) cand = b[s] * A[(s * NC + k) * 64];
-        const double xk = __shfl(cand, base + p % G);
+        const double xk = gbcast<G>(cand, base + p % G);
 #pragma unroll
         for (int s = 0; s < R; s++) {
             if (pstep[s] >= 0 && pstep[s] < k) b[s] -= A[(s * NC + k) * 64] * xk;
