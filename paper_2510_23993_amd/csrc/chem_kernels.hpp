@@ -243,7 +243,7 @@ struct Lane {
     static constexpr int N = M::N;
     double t, tend, h, c_lu, rho;
     int k, neq, att, round_att;
-    bool lu_ok, jac_fresh;
+    bool lu_ok, jac_fresh, last;   // last: the next attempt ends on t_end
     int piv[M::NN];
     // per-lane statistics
     unsigned long long n_steps, n_att, n_rhs, n_jac, n_lu, n_solve;
@@ -301,6 +301,11 @@ __device__ __forceinline__ void rescale(double* D, int64_t ld, int k, double r) 
 
 enum StepResult { SR_RETRY = 0, SR_ACCEPT = 1, SR_DONE = 2, SR_FAIL = 3 };
 
+// Every change of step size (rejections, order and step selection, the
+// clamp of the last step onto t_end) goes through one rescale of D at the
+// end of the attempt: the ratios of successive changes multiply, since each
+// re-samples the same interpolating polynomial.  The last step is flagged
+// there, so the next attempt lands exactly on t_end.
 template <class M>
 __device__ __forceinline__ int bdf_attempt(const Params<M>& P, Lane<M>& L, double* D, int64_t ld, double* A,
                            double rtol, double atol) {
@@ -309,18 +314,14 @@ __device__ __forceinline__ int bdf_attempt(const Params<M>& P, Lane<M>& L, doubl
     L.att++;
     L.round_att++;
     L.n_att++;
-    if (!(L.h >= 10.0 * EPS * fabs(L.t))) return SR_FAIL;
-    bool last = false;
-    if (L.t + L.h >= L.tend) {
-        const double hn = L.tend - L.t;
-        rescale<N>(D, ld, L.k, hn / L.h);
-        L.h = hn;
-        L.neq = 0;
-        last = true;
-    }
+    const bool last = L.last;
     const double tn = last ? L.tend : L.t + L.h;
     const int k = L.k;
     const double gk = gamma_k(k);
+    int res = SR_RETRY;
+    bool resc = false;     // the step size changes by fac for the next attempt
+    double fac = 1.0;
+    double ise[N];
     double yp[N], psi[N], isc[N];
 #pragma unroll
     for (int i = 0; i < N; i++) {
@@ -341,6 +342,7 @@ __device__ __forceinline__ int bdf_attempt(const Params<M>& P, Lane<M>& L, doubl
         isc[i] = 1.0 / (atol + rtol * fabs(a));
     }
     const double c = L.h / gk;
+    bool lu_ready = true;
     if (!L.lu_ok || fabs(c - L.c_lu) > 0.3 * L.c_lu) {
         newton_matrix<M>(P, L.rho, yp, c, A);
         L.n_jac++;
@@ -349,141 +351,155 @@ __device__ __forceinline__ int bdf_attempt(const Params<M>& P, Lane<M>& L, doubl
         L.lu_ok = lu_factor<M::NN, lanes_per_wave<M>()>(A, L.piv);
         L.c_lu = c;
         if (!L.lu_ok) {   // singular even with a fresh Jacobian: shrink the step
-            rescale<N>(D, ld, k, 0.25);
-            L.h *= 0.25;
-            L.neq = 0;
-            return SR_RETRY;
+            fac = 0.25;
+            resc = true;
         }
+        lu_ready = L.lu_ok;
     }
-    const double tol = fmax(10.0 * EPS / rtol, fmin(0.03, sqrt(rtol)));
-    double d[N], yn[N];
-#pragma unroll
-    for (int i = 0; i < N; i++) {
-        d[i] = 0.0;
-        yn[i] = yp[i];
-    }
-    bool conv = false;
-    double dn_old = -1.0;
-    for (int it = 0; it < 4; it++) {
-        double f[N];
-        rhs(P, L.rho, yn, f);
-        L.n_rhs++;
-        bool fin = true;
+    if (lu_ready) {
+        const double tol = fmax(10.0 * EPS / rtol, fmin(0.03, sqrt(rtol)));
+        double d[N], yn[N];
 #pragma unroll
         for (int i = 0; i < N; i++) {
-            f[i] = c * f[i] - psi[i] - d[i];
-            fin = fin && isfinite(f[i]);
+            d[i] = 0.0;
+            yn[i] = yp[i];
         }
-        if (!fin) break;
-        {   // solve on the Newton system; inert components keep the residual (identity rows)
-            double fs[M::NN];
+        bool conv = false;
+        double dn_old = -1.0;
+        for (int it = 0; it < 4; it++) {
+            double f[N];
+            rhs(P, L.rho, yn, f);
+            L.n_rhs++;
+            bool fin = true;
 #pragma unroll
-            for (int s = 0; s < M::NN; s++) fs[s] = f[M::ISYS[s]];
-            lu_solve<M::NN, lanes_per_wave<M>()>(A, L.piv, fs);
+            for (int i = 0; i < N; i++) {
+                f[i] = c * f[i] - psi[i] - d[i];
+                fin = fin && isfinite(f[i]);
+            }
+            if (!fin) break;
+            {   // solve on the Newton system; inert components keep the residual (identity rows)
+                double fs[M::NN];
 #pragma unroll
-            for (int s = 0; s < M::NN; s++) f[M::ISYS[s]] = fs[s];
+                for (int s = 0; s < M::NN; s++) fs[s] = f[M::ISYS[s]];
+                lu_solve<M::NN, lanes_per_wave<M>()>(A, L.piv, fs);
+#pragma unroll
+                for (int s = 0; s < M::NN; s++) f[M::ISYS[s]] = fs[s];
+            }
+            L.n_solve++;
+            const double dn = wrms<N>(f, isc);
+            const double rate = dn_old > 0.0 ? dn / dn_old : -1.0;
+            if (rate >= 0.0) {
+                double rp = 1.0;
+                for (int q = 0; q < 4 - it; q++) rp *= rate;
+                if (rate >= 1.0 || rp / (1.0 - rate) * dn > tol) break;
+            }
+#pragma unroll
+            for (int i = 0; i < N; i++) {
+                yn[i] += f[i];
+                d[i] += f[i];
+            }
+            if (dn == 0.0 || (rate >= 0.0 && rate / (1.0 - rate) * dn < tol)) {
+                conv = true;
+                break;
+            }
+            dn_old = dn;
         }
-        L.n_solve++;
-        const double dn = wrms<N>(f, isc);
-        const double rate = dn_old > 0.0 ? dn / dn_old : -1.0;
-        if (rate >= 0.0) {
-            double rp = 1.0;
-            for (int q = 0; q < 4 - it; q++) rp *= rate;
-            if (rate >= 1.0 || rp / (1.0 - rate) * dn > tol) break;
+        double en = 0.0;
+        if (!conv) {
+            if (!L.jac_fresh) {   // refresh J and LU, same step size
+                L.lu_ok = false;
+            } else {
+                fac = 0.5;
+                resc = true;
+            }
+        } else {
+            // error test
+            double e1[N];
+#pragma unroll
+            for (int i = 0; i < N; i++) {
+                ise[i] = 1.0 / (atol + rtol * fabs(yn[i]));
+                e1[i] = d[i] * (1.0 / (k + 1));
+            }
+            en = wrms<N>(e1, ise);
+            if (en > 1.0) {
+                fac = fmax(0.2, 0.9 * pow(en, -1.0 / (k + 1)));
+                resc = true;
+            }
         }
+        if (conv && en <= 1.0) {
+            // accept: D_{k+2} = d - D_{k+1}, D_{k+1} = d, D_j += D_{j+1} for j = k..0
+            L.n_steps++;
+            L.t = tn;
+            L.jac_fresh = false;
 #pragma unroll
-        for (int i = 0; i < N; i++) {
-            yn[i] += f[i];
-            d[i] += f[i];
-        }
-        if (dn == 0.0 || (rate >= 0.0 && rate / (1.0 - rate) * dn < tol)) {
-            conv = true;
-            break;
-        }
-        dn_old = dn;
-    }
-    if (!conv) {
-        if (!L.jac_fresh) {       // refresh J and LU, same step size
-            L.lu_ok = false;
-            return SR_RETRY;
-        }
-        rescale<N>(D, ld, k, 0.5);
-        L.h *= 0.5;
-        L.neq = 0;
-        return SR_RETRY;
-    }
-    // error test
-    double ise[N], e1[N];
+            for (int i = 0; i < N; i++) {
+                double dv[MAXORD + 3];
 #pragma unroll
-    for (int i = 0; i < N; i++) {
-        ise[i] = 1.0 / (atol + rtol * fabs(yn[i]));
-        e1[i] = d[i] * (1.0 / (k + 1));
-    }
-    const double en = wrms<N>(e1, ise);
-    if (en > 1.0) {
-        const double fac = fmax(0.2, 0.9 * pow(en, -1.0 / (k + 1)));
-        rescale<N>(D, ld, k, fac);
-        L.h *= fac;
-        L.neq = 0;
-        return SR_RETRY;
-    }
-    // accept: D_{k+2} = d - D_{k+1}, D_{k+1} = d, D_j += D_{j+1} for j = k..0
-    L.n_steps++;
-    L.t = tn;
-    L.jac_fresh = false;
+                for (int j = 0; j <= MAXORD + 1; j++) dv[j] = (j <= k + 1) ? D[(j * N + i) * ld] : 0.0;
+                D[((k + 2) * N + i) * ld] = d[i] - D[((k + 1) * N + i) * ld];
+                double acc = d[i];
+                D[((k + 1) * N + i) * ld] = acc;
 #pragma unroll
-    for (int i = 0; i < N; i++) {
-        double dv[MAXORD + 3];
+                for (int j = MAXORD; j >= 0; j--) {
+                    if (j <= k) {
+                        acc = dv[j] + acc;
+                        D[(j * N + i) * ld] = acc;
+                    }
+                }
+            }
+            L.neq++;
+            res = last ? SR_DONE : SR_ACCEPT;
+            if (!last && L.neq >= k + 1) {
+                // order and step-size selection
+                double em = 0.0, ep = 0.0;
+                {
+                    double v[N];
+                    if (k > 1) {
 #pragma unroll
-        for (int j = 0; j <= MAXORD + 1; j++) dv[j] = (j <= k + 1) ? D[(j * N + i) * ld] : 0.0;
-        D[((k + 2) * N + i) * ld] = d[i] - D[((k + 1) * N + i) * ld];
-        double acc = d[i];
-        D[((k + 1) * N + i) * ld] = acc;
+                        for (int i = 0; i < N; i++) v[i] = D[(k * N + i) * ld] * (1.0 / k);
+                        em = wrms<N>(v, ise);
+                    }
+                    if (k < MAXORD) {
 #pragma unroll
-        for (int j = MAXORD; j >= 0; j--) {
-            if (j <= k) {
-                acc = dv[j] + acc;
-                D[(j * N + i) * ld] = acc;
+                        for (int i = 0; i < N; i++) v[i] = D[((k + 2) * N + i) * ld] * (1.0 / (k + 2));
+                        ep = wrms<N>(v, ise);
+                    }
+                }
+                const double f0 = pow(en, -1.0 / (k + 1));
+                const double fm = (k > 1) ? pow(em, -1.0 / k) : 0.0;
+                const double fp = (k < MAXORD) ? pow(ep, -1.0 / (k + 2)) : 0.0;
+                int dk = 0;
+                double best = f0;
+                if (fm > best) {
+                    best = fm;
+                    dk = -1;
+                }
+                if (fp > best) {
+                    best = fp;
+                    dk = 1;
+                }
+                L.k = k + dk;
+                fac = fmin(10.0, 0.9 * best);
+                resc = true;
             }
         }
     }
-    L.neq++;
-    if (last) return SR_DONE;
-    if (L.neq < k + 1) return SR_ACCEPT;
-    // order and step-size selection
-    double em = 0.0, ep = 0.0;
-    {
-        double v[N];
-        if (k > 1) {
-#pragma unroll
-            for (int i = 0; i < N; i++) v[i] = D[(k * N + i) * ld] * (1.0 / k);
-            em = wrms<N>(v, ise);
-        }
-        if (k < MAXORD) {
-#pragma unroll
-            for (int i = 0; i < N; i++) v[i] = D[((k + 2) * N + i) * ld] * (1.0 / (k + 2));
-            ep = wrms<N>(v, ise);
-        }
+    if (res == SR_DONE) return res;
+    // the step size of the next attempt, clamped onto t_end
+    double hn = L.h * fac;
+    if (!(hn >= 10.0 * EPS * fabs(L.t))) return SR_FAIL;
+    L.last = L.t + hn >= L.tend;
+    if (L.last) {
+        fac = (L.tend - L.t) / L.h;
+        hn = L.tend - L.t;
+        resc = true;
     }
-    const double f0 = pow(en, -1.0 / (k + 1));
-    const double fm = (k > 1) ? pow(em, -1.0 / k) : 0.0;
-    const double fp = (k < MAXORD) ? pow(ep, -1.0 / (k + 2)) : 0.0;
-    int dk = 0;
-    double best = f0;
-    if (fm > best) {
-        best = fm;
-        dk = -1;
+    if (resc) {
+        rescale<N>(D, ld, L.k, fac);
+        L.h = hn;
+        L.neq = 0;
     }
-    if (fp > best) {
-        best = fp;
-        dk = 1;
-    }
-    L.k = k + dk;
-    const double fac = fmin(10.0, 0.9 * best);
-    rescale<N>(D, ld, L.k, fac);
-    L.h *= fac;
-    L.neq = 0;
-    return SR_ACCEPT;
+    return res;
 }
 
 // Initial state of a fresh cell: D_0 = y0, D_1 = h f(y0), order 1, with the
@@ -493,15 +509,27 @@ __device__ __forceinline__ void bdf_init(const Params<M>& P, Lane<M>& L, double*
                          double rtol, double atol) {
     constexpr int N = M::N;
     double f0[N], isc[N], y1[N], f1[N];
-    rhs(P, L.rho, y0, f0);
+    double d1 = 0.0, h0 = 0.0;
 #pragma unroll
-    for (int i = 0; i < N; i++) isc[i] = 1.0 / (atol + rtol * fabs(y0[i]));
-    const double d0 = wrms<N>(y0, isc), d1 = wrms<N>(f0, isc);
-    double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
-    h0 = fmin(h0, L.tend);
+    for (int i = 0; i < N; i++) {
+        isc[i] = 1.0 / (atol + rtol * fabs(y0[i]));
+        y1[i] = y0[i];
+    }
+    // f(y0), then f(y0 + h0 f(y0)): one evaluation site for both
+#pragma unroll 1
+    for (int pass = 0; pass < 2; pass++) {
+        rhs(P, L.rho, y1, f1);
+        if (pass == 0) {
 #pragma unroll
-    for (int i = 0; i < N; i++) y1[i] = y0[i] + h0 * f0[i];
-    rhs(P, L.rho, y1, f1);
+            for (int i = 0; i < N; i++) f0[i] = f1[i];
+            const double d0 = wrms<N>(y0, isc);
+            d1 = wrms<N>(f0, isc);
+            h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
+            h0 = fmin(h0, L.tend);
+#pragma unroll
+            for (int i = 0; i < N; i++) y1[i] = y0[i] + h0 * f0[i];
+        }
+    }
     L.n_rhs += 2;
 #pragma unroll
     for (int i = 0; i < N; i++) f1[i] -= f0[i];
@@ -521,6 +549,7 @@ __device__ __forceinline__ void bdf_init(const Params<M>& P, Lane<M>& L, double*
     L.lu_ok = false;
     L.jac_fresh = false;
     L.c_lu = 0.0;
+    L.last = L.h >= L.tend;
 }
 
 // ------------------------------------------------------- integration kernel
@@ -528,7 +557,7 @@ struct SaveArea {             // per active slot, lane-major [field][slot]
     double* D;                // ND * N rows
     double* LU;               // N * N rows
     double* scal;             // 4 rows: t, h, c_lu, (unused)
-    int* ints;                // 4 rows: k, neq, att, flags(lu_ok | jac_fresh<<1)
+    int* ints;                // 4 rows: k, neq, att, flags(lu_ok | jac_fresh<<1 | last<<2)
     int8_t* piv;              // N rows
     int64_t ld;               // capacity (slots)
 };
@@ -646,6 +675,7 @@ __global__ void __launch_bounds__(64) k_integrate(const Params<M>* __restrict__ 
                 const int fl = S.ints[3 * S.ld + slot];
                 L.lu_ok = fl & 1;
                 L.jac_fresh = (fl >> 1) & 1;
+                L.last = (fl >> 2) & 1;
             } else {
                 double y0[N];
 #pragma unroll
@@ -698,7 +728,7 @@ __global__ void __launch_bounds__(64) k_integrate(const Params<M>* __restrict__ 
                 S.ints[0 * S.ld + slot] = L.k;
                 S.ints[1 * S.ld + slot] = L.neq;
                 S.ints[2 * S.ld + slot] = L.att;
-                S.ints[3 * S.ld + slot] = (L.lu_ok ? 1 : 0) | (L.jac_fresh ? 2 : 0);
+                S.ints[3 * S.ld + slot] = (L.lu_ok ? 1 : 0) | (L.jac_fresh ? 2 : 0) | (L.last ? 4 : 0);
                 a.flag[slot] = 1;
                 unfinished++;
             }
