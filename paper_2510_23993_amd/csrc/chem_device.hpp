@@ -318,7 +318,7 @@ __device__ __forceinline__ void rhs(const Params<M>& P, double rho, const double
 // are kept as NS-vectors.
 template <class M, int j, class Acc>
 __device__ __forceinline__ void jac_loop(const Params<M>& P, const CellEval<M>& E, const double* invC,
-                                         const double* uk, double* om, double* dwT, double* dSm,
+                                         double T, double* om, double* dwT, double* dSm,
                                          Acc& acc) {
     if constexpr (j < M::NR) {
         constexpr int TY = M::TYPE[j];
@@ -355,21 +355,21 @@ __device__ __forceinline__ void jac_loop(const Params<M>& P, const CellEval<M>& 
                 const int m = M::RSP[j][i];
                 const double v = s * mul * M::RNU[j][i] * qf * invC[m];
                 acc(k, m, P.W[k] * P.invW[m] * v);
-                dSm[m] += uk[k] * v;
+                dSm[m] += (E.h_RT[k] - 1.0) * T * v;
             }
 #pragma unroll
             for (int i = 0; i < M::NPR[j]; i++) {
                 const int m = M::PSP[j][i];
                 const double v = -s * mul * M::PNU[j][i] * qr * invC[m];
                 acc(k, m, P.W[k] * P.invW[m] * v);
-                dSm[m] += uk[k] * v;
+                dSm[m] += (E.h_RT[k] - 1.0) * T * v;
             }
             if (TY != RX_ELEM) {
 #pragma unroll
                 for (int m = 0; m < M::NS; m++) {
                     const double v = s * P.eff[j][m] * g;
                     acc(k, m, P.W[k] * P.invW[m] * v);
-                    dSm[m] += uk[k] * v;
+                    dSm[m] += (E.h_RT[k] - 1.0) * T * v;
                 }
             }
         };
@@ -378,7 +378,7 @@ __device__ __forceinline__ void jac_loop(const Params<M>& P, const CellEval<M>& 
 #pragma unroll
         for (int i = 0; i < M::NPR[j]; i++) row(M::PSP[j][i], (double)M::PNU[j][i]);
         __builtin_amdgcn_sched_barrier(0);
-        jac_loop<M, j + 1>(P, E, invC, uk, om, dwT, dSm, acc);
+        jac_loop<M, j + 1>(P, E, invC, T, om, dwT, dSm, acc);
     }
 }
 
@@ -397,10 +397,11 @@ __device__ __forceinline__ void jac_eval(const Params<M>& P, double rho, const d
     for (int k = 0; k < NS; k++) {
         const double aC = fmax(fabs(E.C[k]), C_FLOOR);
         invC[k] = (E.C[k] < 0.0) ? -1.0 / aC : 1.0 / aC;
-        uk[k] = (E.h_RT[k] - 1.0) * T;  // u_k / R (molar)
         om[k] = dwT[k] = dSm[k] = 0.0;
     }
-    jac_loop<M, 0>(P, E, invC, uk, om, dwT, dSm, acc);
+    jac_loop<M, 0>(P, E, invC, T, om, dwT, dSm, acc);
+#pragma unroll
+    for (int k = 0; k < NS; k++) uk[k] = (E.h_RT[k] - 1.0) * T;  // u_k / R (molar)
     const double irho = 1.0 / rho;
     double cvs = 0.0, dcvs = 0.0, S = 0.0, cvk[NS];
 #pragma unroll

@@ -322,6 +322,32 @@ __device__ __forceinline__ int bdf_attempt(const Params<M>& P, Lane<M>& L, doubl
     bool resc = false;     // the step size changes by fac for the next attempt
     double fac = 1.0;
     double ise[N];
+    const double c = L.h / gk;
+    bool lu_ready = true;
+    if (!L.lu_ok || fabs(c - L.c_lu) > 0.3 * L.c_lu) {
+        // the predicted state is formed here and again below, so that no
+        // per-component vector stays live across the Jacobian
+        double yj[N];
+#pragma unroll
+        for (int i = 0; i < N; i++) {
+            double a = 0.0;
+#pragma unroll
+            for (int j = 0; j <= MAXORD; j++)
+                if (j <= k) a += D[(j * N + i) * ld];
+            yj[i] = a;
+        }
+        newton_matrix<M>(P, L.rho, yj, c, A);
+        L.n_jac++;
+        L.n_lu++;
+        L.jac_fresh = true;
+        L.lu_ok = lu_factor<M::NN, lanes_per_wave<M>()>(A, L.piv);
+        L.c_lu = c;
+        if (!L.lu_ok) {   // singular even with a fresh Jacobian: shrink the step
+            fac = 0.25;
+            resc = true;
+        }
+        lu_ready = L.lu_ok;
+    }
     double yp[N], psi[N], isc[N];
 #pragma unroll
     for (int i = 0; i < N; i++) {
@@ -340,21 +366,6 @@ __device__ __forceinline__ int bdf_attempt(const Params<M>& P, Lane<M>& L, doubl
         yp[i] = a;
         psi[i] = b / gk;
         isc[i] = 1.0 / (atol + rtol * fabs(a));
-    }
-    const double c = L.h / gk;
-    bool lu_ready = true;
-    if (!L.lu_ok || fabs(c - L.c_lu) > 0.3 * L.c_lu) {
-        newton_matrix<M>(P, L.rho, yp, c, A);
-        L.n_jac++;
-        L.n_lu++;
-        L.jac_fresh = true;
-        L.lu_ok = lu_factor<M::NN, lanes_per_wave<M>()>(A, L.piv);
-        L.c_lu = c;
-        if (!L.lu_ok) {   // singular even with a fresh Jacobian: shrink the step
-            fac = 0.25;
-            resc = true;
-        }
-        lu_ready = L.lu_ok;
     }
     if (lu_ready) {
         const double tol = fmax(10.0 * EPS / rtol, fmin(0.03, sqrt(rtol)));
