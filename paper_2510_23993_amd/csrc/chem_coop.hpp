@@ -724,7 +724,7 @@ __device__ __forceinline__ int cbdf_attempt(const CoopMech& M, const GL& gl, int
     }
     const double en = cwrms<G, R>(e1, ise, n);
     if (en > 1.0) {
-        const double fac = fmax(0.2, 0.9 * pow(en, -1.0 / (k + 1)));
+        const double fac = fmax(0.2, 0.9 * ctl_pow(en, -1.0 / (k + 1)));
         crescale<G, R>(L, k, fac);
         L.h *= fac;
         L.neq = 0;
@@ -778,9 +778,9 @@ __device__ __forceinline__ int cbdf_attempt(const CoopMech& M, const GL& gl, int
             ep = cwrms<G, R>(v, ise, n);
         }
     }
-    const double f0 = pow(en, -1.0 / (k + 1));
-    const double fm = (k > 1) ? pow(em, -1.0 / k) : 0.0;
-    const double fp = (k < MAXORD) ? pow(ep, -1.0 / (k + 2)) : 0.0;
+    const double f0 = ctl_pow(en, -1.0 / (k + 1));
+    const double fm = (k > 1) ? ctl_pow(em, -1.0 / k) : 0.0;
+    const double fp = (k < MAXORD) ? ctl_pow(ep, -1.0 / (k + 2)) : 0.0;
     int dk = 0;
     double best = f0;
     if (fm > best) {

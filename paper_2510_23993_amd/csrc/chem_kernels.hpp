@@ -433,7 +433,7 @@ __device__ __forceinline__ int bdf_attempt(const Params<M>& P, Lane<M>& L, doubl
             }
             en = wrms<N>(e1, ise);
             if (en > 1.0) {
-                fac = fmax(0.2, 0.9 * pow(en, -1.0 / (k + 1)));
+                fac = fmax(0.2, 0.9 * ctl_pow(en, -1.0 / (k + 1)));
                 resc = true;
             }
         }
@@ -476,9 +476,9 @@ __device__ __forceinline__ int bdf_attempt(const Params<M>& P, Lane<M>& L, doubl
                         ep = wrms<N>(v, ise);
                     }
                 }
-                const double f0 = pow(en, -1.0 / (k + 1));
-                const double fm = (k > 1) ? pow(em, -1.0 / k) : 0.0;
-                const double fp = (k < MAXORD) ? pow(ep, -1.0 / (k + 2)) : 0.0;
+                const double f0 = ctl_pow(en, -1.0 / (k + 1));
+                const double fm = (k > 1) ? ctl_pow(em, -1.0 / k) : 0.0;
+                const double fp = (k < MAXORD) ? ctl_pow(ep, -1.0 / (k + 2)) : 0.0;
                 int dk = 0;
                 double best = f0;
                 if (fm > best) {
