@@ -28,16 +28,17 @@ METRIC = "chemistry cell-steps/s, plain FP64 vs batched/mixed/surrogate at fixed
 
 
 # HBM traffic of the bulk-round kernel per call, from two rocprofv3 --pmc
-# passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch summed over the 24
-# launches of one call) on the detonation patch with the options below.  The
-# counters are scaled by what they read for a device copy of known size
-# (151 MB: FETCH_SIZE reads half, WRITE_SIZE reads it exactly).  Valid only
-# for the kernel sources they were taken on (hash below) and these options.
+# passes (FETCH_SIZE, WRITE_SIZE; KiB summed over the 72 launches of three
+# identical calls, 24 launches each) on the detonation patch with the options
+# below.  The counters are scaled by what they read for a device copy of
+# known size (151 MB: FETCH_SIZE reads half, WRITE_SIZE reads it exactly).
+# Valid only for the kernel sources they were taken on (hash below) and
+# these options.
 TRAFFIC_PMC = {
-    "src_sha1": "2126cc9316702bf63fc7a68e0f7abcc3b9125250",
+    "src_sha1": "96debfdabeececf00f43b39dbf0a0fedf4800bfa",
     "options": {"group": 0.0, "max_rounds": 24.0, "nactive_star": 100000.0, "kmax_bulk": 20.0},
-    "fetch_kib": 1424440 + 3744610 + 3318880 + 21 * 16.5, "fetch_factor": 2.0,
-    "write_kib": 3731030 + 6036850 + 4730940, "write_factor": 1.0,
+    "fetch_kib": 1.85707e7 / 3, "fetch_factor": 2.0,
+    "write_kib": 3.81185e7 / 3, "write_factor": 1.0,
 }
 
 
