@@ -348,13 +348,14 @@ __device__ __forceinline__ void coop_rhs(const CoopMech& M, const GL& gl, int l,
     lds_fence();   // the LDS area is reused by the next phase
 }
 
-// Newton matrix rows A = I - c J of the group's cell, left in this lane's LDS
-// row buffer jb: element (s, col) of the lane's own rows at jb[(s*NC + col)*64].
+// Newton matrix rows A = I - c J of the group's cell, left in the group's LDS
+// matrix: row k = l + G*s, column col at jb[col*n + G*s] (jb points at the
+// lane's row 0; column-major over the n rows, rows of lanes k >= n are not
+// stored).
 template <int G, int R>
 __device__ __forceinline__ void coop_newton_matrix(const CoopMech& M, const GL& gl, int l, int base, double rho,
                                    const double* y, double c, double* jb) {
-    constexpr int NC = G * R;
-    const int ns = M.ns;
+    const int ns = M.ns, n = M.n;
     const double T = group_T<G, R>(y, ns, base);
     const double lnT = log(T), invT = 1.0 / T;
     double Ctot, cvs, dcvs;
@@ -369,9 +370,8 @@ __device__ __forceinline__ void coop_newton_matrix(const CoopMech& M, const GL& 
     for (int s = 0; s < R; s++) {
         const int k = l + G * s;
         omk[s] = dwTk[s] = 0.0;
-#pragma unroll
-        for (int col = 0; col < NC; col++) jb[(s * NC + col) * 64] = 0.0;
         if (k < ns) {
+            for (int col = 0; col < ns; col++) jb[col * n + G * s] = 0.0;
             const double Wk = M.sp[(size_t)k * SPS + SP_W];
             double om = 0.0, dwT = 0.0, gd = 0.0;
             for (int p = M.csr_ptr[k]; p < M.csr_ptr[k + 1]; p++) {
@@ -383,25 +383,23 @@ __device__ __forceinline__ void coop_newton_matrix(const CoopMech& M, const GL& 
                 dwT += nu * qj[3];
                 for (int i = 0; i < ri[RI_NRE]; i++) {
                     const int m = ri[RI_RSP + i];
-                    jb[(s * NC + m) * 64] += Wk * M.sp[(size_t)m * SPS + SP_INVW] * nu * ri[RI_RNU + i] * qj[0] * gl.iC[m];
+                    jb[m * n + G * s] += Wk * M.sp[(size_t)m * SPS + SP_INVW] * nu * ri[RI_RNU + i] * qj[0] * gl.iC[m];
                 }
                 for (int i = 0; i < ri[RI_NPR]; i++) {
                     const int m = ri[RI_PSP + i];
-                    jb[(s * NC + m) * 64] -= Wk * M.sp[(size_t)m * SPS + SP_INVW] * nu * ri[RI_PNU + i] * qj[1] * gl.iC[m];
+                    jb[m * n + G * s] -= Wk * M.sp[(size_t)m * SPS + SP_INVW] * nu * ri[RI_PNU + i] * qj[1] * gl.iC[m];
                 }
                 if (ri[RI_TYPE] != RX_ELEM) {   // alpha_m g: ones part (below) + enhanced part
                     const double v = nu * qj[2];
                     gd += v;
                     for (int e = ri[RI_EB]; e < ri[RI_EE]; e++) {
                         const int m = M.eff_sp[e];
-                        jb[(s * NC + m) * 64] += Wk * M.sp[(size_t)m * SPS + SP_INVW] * v * M.eff_am1[e];
+                        jb[m * n + G * s] += Wk * M.sp[(size_t)m * SPS + SP_INVW] * v * M.eff_am1[e];
                     }
                 }
             }
             if (gd != 0.0) {
-#pragma unroll
-                for (int col = 0; col < NC; col++)
-                    if (col < ns) jb[(s * NC + col) * 64] += Wk * M.sp[(size_t)col * SPS + SP_INVW] * gd;
+                for (int col = 0; col < ns; col++) jb[col * n + G * s] += Wk * M.sp[(size_t)col * SPS + SP_INVW] * gd;
             }
             omk[s] = om;
             dwTk[s] = dwT;
@@ -417,12 +415,12 @@ __device__ __forceinline__ void coop_newton_matrix(const CoopMech& M, const GL& 
     // rolled: an unrolled loop over 64 columns (each with a group reduction)
     // makes the kernel larger than the instruction cache
 #pragma unroll 1
-    for (int col = 0; col < NC; col++) {
+    for (int col = 0; col < n; col++) {
         double v = 0.0;
 #pragma unroll
         for (int s = 0; s < R; s++) {
             const int k = l + G * s;
-            if (k < ns) v += (gl.h[k] - 1.0) * T * M.sp[(size_t)k * SPS + SP_INVW] * jb[(s * NC + col) * 64];
+            if (k < ns && col < ns) v += (gl.h[k] - 1.0) * T * M.sp[(size_t)k * SPS + SP_INVW] * jb[col * n + G * s];
         }
         const double dS = (col < ns) ? gsum<G>(v) : 0.0;
 #pragma unroll
@@ -430,7 +428,7 @@ __device__ __forceinline__ void coop_newton_matrix(const CoopMech& M, const GL& 
             const int k = l + G * s;
             double J = 0.0;
             if (k < ns) {
-                if (col < ns) J = jb[(s * NC + col) * 64];
+                if (col < ns) J = jb[col * n + G * s];
                 else if (col == ns) J = M.sp[(size_t)k * SPS + SP_W] * irho * dwTk[s];
             } else if (k == ns) {
                 if (col < ns) {
@@ -440,14 +438,14 @@ __device__ __forceinline__ void coop_newton_matrix(const CoopMech& M, const GL& 
                     J = -E * irho / cvs - fT * dcvs / cvs;
                 }
             }
-            jb[(s * NC + col) * 64] = ((k == col) ? 1.0 : 0.0) - c * J;   // the Newton matrix, in place
+            if (k < n) jb[col * n + G * s] = ((k == col) ? 1.0 : 0.0) - c * J;   // the Newton matrix, in place
         }
     }
     lds_fence();
 }
 
 // LU with implicit partial pivoting of the group's matrix (own rows in the
-// lanes' LDS row buffers A, element (s, col) at A[(s*NC + col)*64]).  After
+// group's LDS matrix A, element (s, col) at A[col*n + G*s]).  After
 // the call: pstep[s] = elimination step at which own row became pivot;
 // gl.perm[k] = pivot row of step k; the pivot row stores 1/pivot on its
 // diagonal and U to its right, other rows keep their multipliers in the
@@ -455,7 +453,6 @@ __device__ __forceinline__ void coop_newton_matrix(const CoopMech& M, const GL& 
 // run to n (not unrolled), which keeps the kernel within the instruction cache.
 template <int G, int R>
 __device__ __forceinline__ bool coop_lu(const GL& gl, int l, int n, double* A, int* pstep) {
-    constexpr int NC = G * R;
     bool ok = true;
 #pragma unroll
     for (int s = 0; s < R; s++) pstep[s] = -1;
@@ -467,7 +464,7 @@ __device__ __forceinline__ bool coop_lu(const GL& gl, int l, int n, double* A, i
         for (int s = 0; s < R; s++) {
             const int i = l + G * s;
             if (i < n && pstep[s] < 0) {
-                const double v = fabs(A[(s * NC + k) * 64]);
+                const double v = fabs(A[k * n + G * s]);
                 if (v > best) {
                     best = v;
                     bidx = i;
@@ -481,7 +478,7 @@ __device__ __forceinline__ bool coop_lu(const GL& gl, int l, int n, double* A, i
         const int sp = p / G;
         if (own) {
 #pragma unroll 4
-            for (int col = k; col < n; col++) gl.prow[col] = A[(sp * NC + col) * 64];
+            for (int col = k; col < n; col++) gl.prow[col] = A[col * n + G * sp];
         }
         lds_fence();
         const double inv = 1.0 / gl.prow[k];
@@ -490,12 +487,12 @@ __device__ __forceinline__ bool coop_lu(const GL& gl, int l, int n, double* A, i
             const int i = l + G * s;
             if (own && s == sp) {
                 pstep[s] = k;
-                A[(s * NC + k) * 64] = inv;
+                A[k * n + G * s] = inv;
             } else if (i < n && pstep[s] < 0) {
-                const double m = A[(s * NC + k) * 64] * inv;
-                A[(s * NC + k) * 64] = m;
+                const double m = A[k * n + G * s] * inv;
+                A[k * n + G * s] = m;
 #pragma unroll 4
-                for (int col = k + 1; col < n; col++) A[(s * NC + col) * 64] -= m * gl.prow[col];
+                for (int col = k + 1; col < n; col++) A[col * n + G * s] -= m * gl.prow[col];
             }
         }
         if (l == 0) gl.perm[k] = p;
@@ -510,14 +507,13 @@ __device__ __forceinline__ bool coop_lu(const GL& gl, int l, int n, double* A, i
 template <int G, int R>
 __device__ __forceinline__ void coop_solve(const GL& gl, int l, int base, int n, const double* A, const int* pstep,
                                            double* b) {
-    constexpr int NC = G * R;
 #pragma unroll 1
     for (int k = 0; k < n; k++) {
         const int p = gl.perm[k];
         const double z = gbcast<G>(rsel<R>(b, p / G), base + p % G);
 #pragma unroll
         for (int s = 0; s < R; s++)
-            if (pstep[s] > k) b[s] -= A[(s * NC + k) * 64] * z;
+            if (pstep[s] > k) b[s] -= A[k * n + G * s] * z;
     }
     double x[R];
 #pragma unroll
@@ -529,11 +525,11 @@ __device__ __forceinline__ void coop_solve(const GL& gl, int l, int base, int n,
         double cand = 0.0;
 #pragma unroll
         for (int s = 0; s < R; s++)
-            if (pstep[s] == k) cand = b[s] * A[(s * NC + k) * 64];
+            if (pstep[s] == k) cand = b[s] * A[k * n + G * s];
         const double xk = gbcast<G>(cand, base + p % G);
 #pragma unroll
         for (int s = 0; s < R; s++) {
-            if (pstep[s] >= 0 && pstep[s] < k) b[s] -= A[(s * NC + k) * 64] * xk;
+            if (pstep[s] >= 0 && pstep[s] < k) b[s] -= A[k * n + G * s] * xk;
             if (l + G * s == k) x[s] = xk;
         }
     }
@@ -1016,7 +1012,7 @@ __global__ void __launch_bounds__(64, 2) k_integrate_coop(CoopArgs a) {
         asm volatile("" : "+v"(lv));
         const int l = lv % G, grp = lv / G, base = grp * G;
         GL gl(lds + grp * a.gl_stride, a.nsp, M.nr, NC);
-        double* jb = lds + NGRP * a.gl_stride + lv;
+        double* jb = lds + NGRP * a.gl_stride + grp * n * n + l;
         if (g < 0) {
             g = (MODE == PLAIN) ? cur : (int64_t)a.active_ids[slot];
             bidx = find_box(a.boxes, a.nbox, g);
@@ -1032,8 +1028,8 @@ __global__ void __launch_bounds__(64, 2) k_integrate_coop(CoopArgs a) {
                     const int c = l + G * q;
 #pragma unroll
                     for (int j = 0; j < ND; j++) L.D[j][q] = S.D[(j * NC + c) * S.ld + slot];
-#pragma unroll 4
-                    for (int col = 0; col < NC; col++) jb[(q * NC + col) * 64] = S.A[(c * NC + col) * S.ld + slot];
+                    if (c < n)
+                        for (int col = 0; col < n; col++) jb[col * n + G * q] = S.A[(c * NC + col) * S.ld + slot];
                     L.pstep[q] = S.ints[c * S.ld + slot];
                     if (L.pstep[q] >= 0) gl.perm[L.pstep[q]] = c;
                 }
@@ -1096,8 +1092,8 @@ __global__ void __launch_bounds__(64, 2) k_integrate_coop(CoopArgs a) {
                     const int c = l + G * q;
 #pragma unroll
                     for (int j = 0; j < ND; j++) S.D[(j * NC + c) * S.ld + slot] = L.D[j][q];
-#pragma unroll 4
-                    for (int col = 0; col < NC; col++) S.A[(c * NC + col) * S.ld + slot] = jb[(q * NC + col) * 64];
+                    if (c < n)
+                        for (int col = 0; col < n; col++) S.A[(c * NC + col) * S.ld + slot] = jb[col * n + G * q];
                     S.ints[c * S.ld + slot] = L.pstep[q];
                 }
                 if (l == 0) {
@@ -1153,10 +1149,10 @@ __global__ void __launch_bounds__(64) k_eval_coop(CoopMech M, int gl_stride, int
     extern __shared__ double lds[];
     const int lane = threadIdx.x, l = lane % G, grp = lane / G, base = grp * G;
     GL gl(lds + grp * gl_stride, nsp, M.nr, NC);
-    double* jb = lds + NGRP * gl_stride + lane;
+    const int n = M.n;
+    double* jb = lds + NGRP * gl_stride + grp * n * n + l;
     const int64_t c = blockIdx.x * (int64_t)NGRP + grp;
     if (c >= ncell) return;   // whole groups exit together
-    const int n = M.n;
     double yy[R], ff[R];
 #pragma unroll
     for (int q = 0; q < R; q++) {
@@ -1177,7 +1173,7 @@ __global__ void __launch_bounds__(64) k_eval_coop(CoopMech M, int gl_stride, int
             const int i = l + G * q;
             if (i < n) {
                 for (int col = 0; col < n; col++)
-                    J[(i * n + col) * ncell + c] = jb[(q * NC + col) * 64] - (i == col ? 1.0 : 0.0);
+                    J[(i * n + col) * ncell + c] = jb[col * n + G * q] - (i == col ? 1.0 : 0.0);
             }
         }
     }

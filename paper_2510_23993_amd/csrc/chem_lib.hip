@@ -501,10 +501,12 @@ int coop_R(int G) {
     return 0;
 }
 
+// per workgroup: 64/G groups, each with its species/reaction scratch and its
+// n x n Newton matrix
 int coop_lds_bytes(const chem_mech_s* m, int G) {
-    const int R = coop_R(G), NC = G * R;
+    const int R = coop_R(G), NC = G * R, n = m->hm.ns + 1;
     const int gl = group_lds_doubles(m->hm.ns, (int)m->hm.rx.size(), NC);
-    return 8 * ((64 / G) * gl + 64 * R * NC);
+    return 8 * ((64 / G) * (gl + n * n));
 }
 
 template <int G, int R, int MODE>
