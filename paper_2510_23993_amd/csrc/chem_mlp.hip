@@ -298,6 +298,8 @@ __global__ void k_to_bf16_frag(const float* __restrict__ W, int nout, int nblk, 
 
 // One 32-row tile through a 256 -> 32*NB dense layer: A from the LDS tile,
 // B fragments from global memory (L2-resident weights), FP32 accumulators.
+// The fragments of the next k-step are in flight while the current step's
+// products run, which hides most of the L2 latency of a wave.
 template <int NB>
 __device__ __forceinline__ void tile_mfma(const uint16_t* __restrict__ Hs, const uint16_t* __restrict__ F, int lane,
                                           f32x16 (&acc)[NB]) {
@@ -307,13 +309,20 @@ __device__ __forceinline__ void tile_mfma(const uint16_t* __restrict__ Hs, const
     for (int nb = 0; nb < NB; nb++)
 #pragma unroll
         for (int q = 0; q < 16; q++) acc[nb][q] = 0.f;
+    bf16x4 bn[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; nb++) bn[nb] = Fv[nb * 64 + lane];
     for (int kb = 0; kb < NH / 8; kb++) {
         const bf16x4 a = *(const bf16x4*)(Hs + r * HS + kb * 8 + kh);
+        bf16x4 bc[NB];
 #pragma unroll
-        for (int nb = 0; nb < NB; nb++) {
-            const bf16x4 b = Fv[((int64_t)kb * NB + nb) * 64 + lane];
-            acc[nb] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc[nb], 0, 0, 0);
+        for (int nb = 0; nb < NB; nb++) bc[nb] = bn[nb];
+        if (kb + 1 < NH / 8) {
+#pragma unroll
+            for (int nb = 0; nb < NB; nb++) bn[nb] = Fv[((int64_t)(kb + 1) * NB + nb) * 64 + lane];
         }
+#pragma unroll
+        for (int nb = 0; nb < NB; nb++) acc[nb] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, bc[nb], acc[nb], 0, 0, 0);
     }
 }
 
@@ -328,6 +337,15 @@ __global__ void __launch_bounds__(64) k_mlp_infer(MlpDev w, int64_t rows_host, c
     const int64_t rows = rows_dev ? (int64_t)*rows_dev : rows_host;
     const int64_t ntile = (rows + 31) / 32;
     const float* p = w.p;
+    // first-layer weights and biases of this lane's outputs, loaded once
+    float w1[4][NIN], b1[4];
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const int j = lane + 64 * q;
+#pragma unroll
+        for (int k = 0; k < NIN; k++) w1[q][k] = p[OW1 + j * NIN + k];
+        b1[q] = p[OB1 + j];
+    }
     for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
         const int64_t r0 = tile * 32;
         for (int e = lane; e < 32 * NIN; e += 64) {
@@ -339,14 +357,10 @@ __global__ void __launch_bounds__(64) k_mlp_infer(MlpDev w, int64_t rows_host, c
 #pragma unroll
         for (int q = 0; q < 4; q++) {
             const int j = lane + 64 * q;
-            float wj[NIN];
-#pragma unroll
-            for (int k = 0; k < NIN; k++) wj[k] = p[OW1 + j * NIN + k];
-            const float bj = p[OB1 + j];
             for (int r = 0; r < 32; r++) {
-                float z = bj;
+                float z = b1[q];
 #pragma unroll
-                for (int k = 0; k < NIN; k++) z = fmaf(wj[k], Xs[r * NIN + k], z);
+                for (int k = 0; k < NIN; k++) z = fmaf(w1[q][k], Xs[r * NIN + k], z);
                 Hs[r * HS + j] = f2bf(gelu(z));
             }
         }
