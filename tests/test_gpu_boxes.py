@@ -155,3 +155,55 @@ def test_autotune_restores_state_and_caches(chem, mech, small_boxes, tmp_path):
     assert len(open(cache).read().strip().splitlines()) == 1
     st = ctx2.integrate_boxes(d, RTOL_C1, 1e-20)
     assert st["rc"] == 0
+
+
+def test_full_hierarchy_sample_vs_oracle(chem, mech, m9):
+    """All 400 boxes of the three-level hierarchy (5,750,784 cells) in one
+    graph-replayed pipeline with the options the autotuner picks for it (one
+    lane per cell, no bulk rounds), at the benchmark's tolerances (rtol 1e-8,
+    atol 1e-14).  300 sampled integrated cells against the oracle at tight
+    tolerance: relative bound where the relative tolerance dominates
+    (Y > atol/rtol), temperature everywhere."""
+    import torch
+    atol = 1e-14
+    boxes = fields.c3_boxes()
+    hb, d = [], []
+    for i, b in enumerate(boxes):
+        c = fields.c3_box_state(b, box_id=i)
+        rho, e = m9.state_from_TPY(c.T, c.p, c.Y)
+        hb.append(dict(rho=rho, e=e, Y=c.Y, T=c.T, dt=c.dt))
+        n = c.T.size
+        d.append(dict(rho=to_dev(rho), e=to_dev(e), Y=to_dev(c.Y), T=to_dev(c.T),
+                      status=torch.full((n,), 255, dtype=torch.uint8, device="cuda"), dt=c.dt, level=b.level))
+    assert sum(b["rho"].size for b in hb) == 5750784
+    ctx = chem.Context(mech, use_graph=1, group=0, max_rounds=0, nactive_star=1e4, kmax_bulk=5)
+    st = ctx.integrate_boxes(d, RTOL_C1, atol)
+    assert st["rc"] == 0
+    rng = np.random.default_rng(11)
+    picks = {}
+    for _ in range(300):
+        while True:
+            bi = int(rng.integers(len(hb)))
+            s = host(d[bi]["status"])
+            ok = np.where(s == chem.ST_DONE)[0]
+            if ok.size:
+                picks.setdefault(bi, set()).add(int(rng.choice(ok)))
+                break
+    worst_rel = worst_dT = 0.0
+    compared = 0
+    for bi, cells in picks.items():
+        idx = np.array(sorted(cells))
+        b = hb[bi]
+        Yr, Tr, so = m9.integrate(b["rho"][idx], b["e"][idx], b["Y"][:, idx], b["dt"], JUDGE_RTOL, JUDGE_ATOL,
+                                  T=b["T"][idx])
+        assert np.all(so == 0)
+        Yg, Tg = host(d[bi]["Y"])[:, idx], host(d[bi]["T"])[idx]
+        _, dT, relmat = parity_report(Yg, Tg, Yr, Tr)
+        dom = Yr > atol / RTOL_C1
+        worst_rel = max(worst_rel, float(np.where(dom, relmat, 0.0).max()))
+        worst_dT = max(worst_dT, dT)
+        compared += idx.size
+    print(f"full hierarchy vs oracle ({compared} cells in {len(picks)} boxes, {st['t_total_ms']:.1f} ms): "
+          f"max rel (Y > 1e-6) {worst_rel:.3e}, max |dT| {worst_dT:.3e} K")
+    assert compared >= 250
+    assert worst_rel <= SPECIES_REL and worst_dT <= T_ABS
