@@ -158,7 +158,12 @@ void chem_ctx_destroy(chem_ctx_t c);
  *   surrogate     1 = run the learned surrogate on the active cells before the
  *                 implicit integration (needs chem_load_surrogate and algorithm 1);
  *                 cells failing its trust check are integrated, default 0
- *   surr_rtol     relative tolerance of the surrogate's consistency check, default 1e-4
+ *   surr_rtol     relative tolerance of the surrogate's consistency check, default
+ *                 1e-6: the check does not see network errors that scale with
+ *                 the step (they cancel between the one-step and two-step
+ *                 predictions), and on the 8.4M-cell evaluation field it
+ *                 accepted cells 10-200x over their tolerance at 1e-4, so the
+ *                 default is two orders below a 1e-4 error budget
  * Returns CHEM_E_INVAL for an unknown key or out-of-range value. */
 int chem_set_option(chem_ctx_t c, const char* key, double value);
 int chem_get_option(chem_ctx_t c, const char* key, double* value);

@@ -53,7 +53,7 @@ struct Options {
     int use_graph = 1;
     int group = -1;   // lanes per cell: 0 = compiled one-lane kernel, 4..64 = cooperative, -1 = auto
     int surrogate = 0;        // 1 = surrogate pass before the implicit integration
-    double surr_rtol = 1e-4;  // relative tolerance of the surrogate's consistency check
+    double surr_rtol = 1e-6;  // relative tolerance of the surrogate's consistency check
     bool operator==(const Options& o) const { return !memcmp(this, &o, sizeof(Options)); }
 };
 

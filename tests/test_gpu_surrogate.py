@@ -92,9 +92,14 @@ def _errors(m9, c, rho, e, Yg, Tg, idx):
     return rel, np.abs(Tg[idx] - Tr)
 
 
+def test_default_trust_tolerance(chem, mech):
+    ctx = chem.Context(mech)
+    assert ctx.get_option("surr_rtol") == 1e-6
+
+
 def test_cells_within_budget_at_default_trust(chem, mech, m9, weights):
-    """At the default trust tolerance (1e-4, the error budget) every cell,
-    accepted or integrated after rejection, meets the budget."""
+    """At the default trust tolerance (1e-6, two orders below the budget)
+    every cell, accepted or integrated after rejection, meets the budget."""
     c = fields.c2_field(256, 24, 2, seed=1005)
     rho, e = oracle_inputs(m9, c)
     Yg, Tg, sg, st = _run(chem, mech, c, rho, e, weights)
@@ -135,3 +140,23 @@ def test_surrogate_gain_at_loose_trust(chem, mech, m9, weights):
     assert rel.max() <= 0.5 and dT.max() <= 5.0
     # accepted cells conserve mass to rounding
     assert np.allclose(Yg[:, ok].sum(axis=0), c.Y[:, ok].sum(axis=0), rtol=0, atol=1e-12)
+
+
+def test_full_size_evaluation_field_within_budget(chem, mech, m9, weights):
+    """The evaluation field at the configuration's size (256 x 256 x 128 =
+    8,388,608 cells) at the default trust tolerance: sampled accepted and
+    fallback cells meet the 1e-4 / 1 K budget against the oracle."""
+    c = fields.c2_field(256, 256, 128, seed=1005)
+    assert c.T.size == 8388608
+    rho, e = oracle_inputs(m9, c)
+    Yg, Tg, sg, st = _run(chem, mech, c, rho, e, weights)
+    assert st["rc"] == 0
+    ok = np.where(sg == chem.ST_SURR_OK)[0]
+    rej = np.where(sg == chem.ST_SURR_REJ)[0]
+    assert ok.size + rej.size == (c.cls > 0).sum()
+    rng = np.random.default_rng(17)
+    idx = np.sort(np.concatenate([ok, rng.choice(rej, 150, replace=False)])).astype(np.int64)
+    rel, dT = _errors(m9, c, rho, e, Yg, Tg, idx)
+    print(f"8.4M-cell field: accepted {ok.size}, fell back {rej.size}, {st['t_total_ms']:.1f} ms; "
+          f"{idx.size} sampled: max rel {rel.max():.2e}, max |dT| {dT.max():.2e} K")
+    assert rel.max() <= BUDGET_REL and dT.max() <= BUDGET_T
