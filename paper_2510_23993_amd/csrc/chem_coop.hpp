@@ -542,7 +542,7 @@ template <int G, int R>
 struct CLane {
     static constexpr int NC = G * R;
     double D[ND][R];
-    int pstep[R];   // the matrix rows live in the lane's LDS row buffer
+    int pstep[R];   // the matrix rows live in the group's LDS matrix
     double t, tend, h, c_lu, rho;
     int k, neq, att, round_att;
     bool lu_ok, jac_fresh;
@@ -1166,7 +1166,7 @@ __global__ void __launch_bounds__(64) k_eval_coop(CoopMech M, int gl_stride, int
         if (i < n) f[i * ncell + c] = ff[q];
     }
     if (J) {
-        // c = -1 gives A = I + J in the row buffer
+        // c = -1 gives A = I + J in the group's LDS matrix
         coop_newton_matrix<G, R>(M, gl, l, base, rho[c], yy, -1.0, jb);
 #pragma unroll
         for (int q = 0; q < R; q++) {
