@@ -158,6 +158,16 @@ void chem_ctx_destroy(chem_ctx_t c);
  *   surrogate     1 = run the learned surrogate on the active cells before the
  *                 implicit integration (needs chem_load_surrogate and algorithm 1);
  *                 cells failing its trust check are integrated, default 0
+ *   method        0 = variable-order BDF (default); 1 = the paper's explicit
+ *                 first-order scheme (Sec. 2.1, Alg. 2): Y <- Y + h dY/dt with h
+ *                 the largest step that changes no mass fraction by more than
+ *                 explicit_frac of max(|Y_k|, 1e-10), T from e by Newton after
+ *                 every step, the last step ending at dt; rtol and atol are
+ *                 not used, kmax_sparse bounds the steps per cell.  Runs one
+ *                 lane per cell (compiled mechanisms only, CHEM_E_INVAL
+ *                 otherwise), after the same screen and compaction
+ *   explicit_frac largest relative change per explicit step, 1e-6 .. 0.05,
+ *                 default 0.01
  *   surr_rtol     relative tolerance of the surrogate's consistency check, default
  *                 1e-6: the check does not see network errors that scale with
  *                 the step (they cancel between the one-step and two-step

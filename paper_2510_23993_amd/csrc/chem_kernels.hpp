@@ -774,4 +774,90 @@ __global__ void __launch_bounds__(64) k_integrate(const Params<M>* __restrict__ 
     }
 }
 
+// --------------------------------------------- explicit scheme (Sec. 2.1)
+// The paper's first-order kinetics steps: Y <- Y + h S with S = dY/dt
+// (Eq. 5) and h the largest step for which no mass fraction changes by more
+// than frac of max(|Y_k|, y_floor); T follows from the fixed e by Newton
+// after every step (Alg. 2); the last step ends exactly at dt.  One lane per
+// cell over the compacted active list.
+struct ExpArgs {
+    const DevBox* boxes;
+    int nbox;
+    uint8_t* st_int;
+    const int* active_ids;
+    const int* n_items_dev;
+    const uint8_t* flag;      // per slot: 2 = taken by the surrogate pass
+    int kmax;
+    double frac, y_floor;
+    Counters* ctr;
+};
+
+template <class M>
+__global__ void __launch_bounds__(64) k_explicit(const Params<M>* __restrict__ Pp, ExpArgs a) {
+    constexpr int N = M::N, NS = M::NS;
+    const Params<M>& P = *Pp;
+    const int n = *a.n_items_dev;
+    unsigned long long steps = 0, max_steps = 0, incomplete = 0;
+    for (int s = blockIdx.x * 64 + threadIdx.x; s < n; s += gridDim.x * 64) {
+        if (a.flag[s] == 2) continue;
+        const int64_t g = a.active_ids[s];
+        const DevBox& B = a.boxes[find_box(a.boxes, a.nbox, g)];
+        const int64_t i = g - B.off;
+        const double rho = B.rho[i], e0 = B.e[i], dt = B.dt;
+        double y[N];
+#pragma unroll
+        for (int k = 0; k < NS; k++) y[k] = B.Y[k * B.ldY + i];
+        y[NS] = B.T[i];   // from the screen's inversion of e
+        double t = 0.0;
+        int k = 0;
+        uint8_t st = ST_DONE;
+        for (;;) {
+            if (k >= a.kmax) {
+                st = ST_KMAX;
+                break;
+            }
+            double f[N];
+            rhs(P, rho, y, f);
+            double h = dt - t;
+#pragma unroll
+            for (int q = 0; q < NS; q++)
+                if (f[q] != 0.0) h = fmin(h, a.frac * fmax(fabs(y[q]), a.y_floor) / fabs(f[q]));
+            const bool last = h >= dt - t;
+#pragma unroll
+            for (int q = 0; q < NS; q++) y[q] += h * f[q];
+            t = last ? dt : t + h;
+            k++;
+            double Tn;
+            if (!T_from_e(P, e0, y, y[NS], Tn)) {
+                st = ST_TINV;
+                break;
+            }
+            y[NS] = Tn;
+            if (last) break;
+        }
+#pragma unroll
+        for (int q = 0; q < NS; q++) B.Y[q * B.ldY + i] = y[q];
+        B.T[i] = y[NS];
+        const uint8_t fin = (st == ST_DONE && a.st_int[g] == ST_SURR_REJ) ? (uint8_t)ST_SURR_REJ : st;
+        a.st_int[g] = fin;
+        if (B.status) B.status[i] = fin;
+        steps += k;
+        max_steps = max(max_steps, (unsigned long long)k);
+        if (st != ST_DONE) incomplete++;
+    }
+    for (int o = 32; o >= 1; o >>= 1) {
+        steps += __shfl_xor(steps, o);
+        incomplete += __shfl_xor(incomplete, o);
+        max_steps = max(max_steps, (unsigned long long)__shfl_xor(max_steps, o));
+    }
+    if (threadIdx.x == 0) {
+        Counters* ct = a.ctr;
+        atomicAdd(&ct->steps, steps);
+        atomicAdd(&ct->attempts, steps);
+        atomicAdd(&ct->rhs, steps);
+        atomicMax(&ct->max_attempts, max_steps);
+        atomicAdd(&ct->incomplete, incomplete);
+    }
+}
+
 }  // namespace chem

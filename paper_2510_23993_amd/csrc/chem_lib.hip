@@ -38,6 +38,7 @@ int fail(int code, const std::string& msg) {
     } while (0)
 
 constexpr int RMAX = 64;  // most bulk-round launches per pipeline
+constexpr double EXPLICIT_Y_FLOOR = 1e-10;   // floor under the explicit scheme's relative step limit
 // device int counters
 enum { I_NACT = 0, I_NSP = 1, I_ROUNDS = 2, I_Q = 4, I_UNF = I_Q + RMAX + 2, I_COUNT = I_UNF + RMAX };
 
@@ -54,6 +55,8 @@ struct Options {
     int group = -1;   // lanes per cell: 0 = compiled one-lane kernel, 4..64 = cooperative, -1 = auto
     int surrogate = 0;        // 1 = surrogate pass before the implicit integration
     double surr_rtol = 1e-6;  // relative tolerance of the surrogate's consistency check
+    int method = 0;           // 0 = variable-order BDF, 1 = the explicit first-order scheme
+    double explicit_frac = 0.01;  // explicit scheme: largest relative change of a mass fraction per step
     bool operator==(const Options& o) const { return !memcmp(this, &o, sizeof(Options)); }
 };
 
@@ -288,7 +291,7 @@ int pipeline_k(chem_ctx_s* c, int64_t total, int nbox, double rtol, double atol)
     a.ctr = ctr;
     a.nstar = o.nactive_star;
     a.rounds = I + I_ROUNDS;
-    if (o.algorithm == 0) {
+    if (o.algorithm == 0 && o.method == 0) {
         a.n_items_host = total;
         a.kmax = o.kmax_sparse;
         mark(c, 2);
@@ -306,6 +309,24 @@ int pipeline_k(chem_ctx_s* c, int64_t total, int nbox, double rtol, double atol)
         rc = c->m->ops->surrogate(c, total, nbox, atol);
         if (rc) return rc;
         mark(c, 4);
+    }
+    if (o.method == 1) {
+        ExpArgs x{};
+        x.boxes = db;
+        x.nbox = nbox;
+        x.st_int = c->st_int.as<uint8_t>();
+        x.active_ids = c->active.as<int>();
+        x.n_items_dev = I + I_NACT;
+        x.flag = c->flag.as<uint8_t>();
+        x.kmax = o.kmax_sparse;
+        x.frac = o.explicit_frac;
+        x.y_floor = EXPLICIT_Y_FLOOR;
+        x.ctr = ctr;
+        mark(c, 0);
+        mark(c, 1);
+        mark(c, 2);
+        hipLaunchKernelGGL((k_explicit<K>), dim3(grid), dim3(64), 0, s, PK, x);
+        return 0;
     }
     const int rounds = std::min(o.max_rounds, RMAX);
     mark(c, 0);
@@ -560,6 +581,7 @@ constexpr int64_t ONE_LANE_MIN_CELLS = 65536;
 int resolve_group(const chem_ctx_s* c, int64_t total) {
     const int n = c->m->hm.ns + 1;
     const int coop = (n <= 16) ? 16 : 64;
+    if (c->opt.method == 1) return 0;   // the explicit scheme runs one lane per cell
     int G = c->opt.group;
     if (G < 0) G = (c->m->ops && total >= ONE_LANE_MIN_CELLS) ? 0 : coop;
     if (G == 0 && !c->m->ops) G = coop;
@@ -1053,6 +1075,10 @@ int chem_set_option(chem_ctx_t c, const char* key, double v) {
         if (v == 1 && !c->s_loaded) return fail(CHEM_E_STATE, "no surrogate loaded");
         o.surrogate = (int)v;
     } else if (k == "surr_rtol" && in(1e-12, 1.0)) o.surr_rtol = v;
+    else if (k == "method" && (v == 0 || v == 1)) {
+        if (v == 1 && !c->m->ops) return fail(CHEM_E_INVAL, "the explicit scheme needs a compiled mechanism");
+        o.method = (int)v;
+    } else if (k == "explicit_frac" && in(1e-6, 0.05)) o.explicit_frac = v;
     else if (k == "group" && (v == -1 || v == 0 || v == 4 || v == 8 || v == 16 || v == 32 || v == 64)) {
         if (v == 0 && !c->m->ops) return fail(CHEM_E_INVAL, "no compiled one-lane kernel for this mechanism");
         o.group = (int)v;
@@ -1076,6 +1102,8 @@ int chem_get_option(chem_ctx_t c, const char* key, double* v) {
     else if (k == "group") *v = o.group;
     else if (k == "surrogate") *v = o.surrogate;
     else if (k == "surr_rtol") *v = o.surr_rtol;
+    else if (k == "method") *v = o.method;
+    else if (k == "explicit_frac") *v = o.explicit_frac;
     else return fail(CHEM_E_INVAL, "unknown option: " + k);
     return CHEM_OK;
 }
