@@ -35,10 +35,10 @@ METRIC = "chemistry cell-steps/s, plain FP64 vs batched/mixed/surrogate at fixed
 # Valid only for the kernel sources they were taken on (hash below) and
 # these options.
 TRAFFIC_PMC = {
-    "src_sha1": "41555e71e3c418f1255061fdd90893843954d128",
+    "src_sha1": "45cb0be3312f295217e9fcaedc2eda6df81f1a4e",
     "options": {"group": 0.0, "max_rounds": 24.0, "nactive_star": 100000.0, "kmax_bulk": 20.0},
-    "fetch_kib": 1.85798e7 / 3, "fetch_factor": 2.0,
-    "write_kib": 3.81385e7 / 3, "write_factor": 1.0,
+    "fetch_kib": 1.85931e7 / 3, "fetch_factor": 2.0,
+    "write_kib": 3.80901e7 / 3, "write_factor": 1.0,
 }
 
 
