@@ -285,8 +285,10 @@ def bench_amr(args, torch, chem, fields):
     """400 seeded AMR boxes over three levels (about 6M cells, dt 4e-8 / 2e-8 /
     1e-8 s by level), jet-in-crossflow-like field.  Times K steps of: one
     launch per box (chem_integrate per box), one chem_integrate_boxes replayed
-    from a hipGraph with default options, and the same after chem_autotune.
-    Every step restarts from a pristine device copy (inside the timed region)."""
+    from a hipGraph with default options, and the same after chem_autotune;
+    then the subcycled coarse step (level 0 once, level 1 twice, level 2 four
+    times, each with its own dt).  Every step restarts from a pristine device
+    copy (inside the timed region)."""
     boxes = fields.c3_boxes()
     mech = chem.Mechanism(fields.M9_PATH)
     stream = torch.cuda.Stream()
@@ -344,6 +346,20 @@ def bench_amr(args, torch, chem, fields):
         tuned_opts, tune_ms = tuned.autotune(dev_boxes, args.rtol, args.atol)
         t_tune = time.perf_counter() - t0
         res["graph_autotuned"] = timed(lambda: tuned.integrate_boxes(dev_boxes, args.rtol, args.atol, stats=False))
+        # subcycled: per coarse step, level 0 once, level 1 twice and level 2
+        # four times, each with its own dt (one graph per box table)
+        l12 = [d for d in dev_boxes if d["level"] >= 1]
+        l2 = [d for d in dev_boxes if d["level"] == 2]
+        c12 = chem.Context(mech, stream=stream, use_graph=1, **tuned_opts)
+        c2 = chem.Context(mech, stream=stream, use_graph=1, **tuned_opts)
+
+        def subcycled():
+            tuned.integrate_boxes(dev_boxes, args.rtol, args.atol, stats=False)
+            c12.integrate_boxes(l12, args.rtol, args.atol, stats=False)
+            c2.integrate_boxes(l2, args.rtol, args.atol, stats=False)
+            c2.integrate_boxes(l2, args.rtol, args.atol, stats=False)
+        res["subcycled_graph_autotuned"] = timed(subcycled)
+        sub_cells = sum(d["rho"].numel() * (1 << d["level"]) for d in dev_boxes)
         # counters and phase times of one eager call with the tuned options
         tuned.set_option("use_graph", 0)
         reset()
@@ -370,6 +386,9 @@ def bench_amr(args, torch, chem, fields):
         "event_ms_per_step": ev_ms,
         "variants_ms_per_step": {k: {"wall": v[0], "events": v[1]} for k, v in res.items()},
         "speedup_graph_autotuned_vs_per_box": res["per_box_launches"][0] / wall_ms,
+        "subcycled": {"cell_steps_per_coarse_step": sub_cells,
+                      "ms_per_coarse_step": res["subcycled_graph_autotuned"][0],
+                      "cell_steps_per_s": sub_cells / (res["subcycled_graph_autotuned"][0] * 1e-3)},
         "stats": {k: st[k] for k in ("n_active0", "n_active_after_bulk", "n_bulk_rounds", "steps_total",
                                      "attempts_total", "t_total_ms", "t_screen_ms", "t_bulk_ms", "t_sparse_ms")},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
