@@ -158,6 +158,10 @@ void chem_ctx_destroy(chem_ctx_t c);
  *   surrogate     1 = run the learned surrogate on the active cells before the
  *                 implicit integration (needs chem_load_surrogate and algorithm 1);
  *                 cells failing its trust check are integrated, default 0
+ *   round_decay   0 .. 0.99, default 0 (off): besides the N* gate, the bulk
+ *                 rounds stop once a round retires less than this fraction of
+ *                 the cells it started with (the active count's decay decides
+ *                 the number of rounds); results do not depend on it
  *   method        0 = variable-order BDF (default); 1 = the paper's explicit
  *                 first-order scheme (Sec. 2.1, Alg. 2): Y <- Y + h dY/dt with h
  *                 the largest step that changes no mass fraction by more than

@@ -942,6 +942,8 @@ struct CoopArgs {
     int* unfinished;
     int* rounds;
     const int* gate;
+    const int* gate_prev;  // the count one round earlier (decay gate)
+    double keep;           // stop the rounds once a round keeps more than keep of its cells
     int nstar;
     uint8_t* flag;
     CoopSave sv;
@@ -961,6 +963,7 @@ __global__ void __launch_bounds__(64, 2) k_integrate_coop(CoopArgs a) {
     if (MODE == BULK) {
         if (*a.n_items_dev == 0) return;
         if (a.gate && *a.gate <= a.nstar) return;
+        if (a.gate_prev && (double)*a.gate > a.keep * (double)*a.gate_prev) return;
         if (blockIdx.x == 0 && lane == 0) atomicAdd(a.rounds, 1);
     }
     const int64_t n_items = (MODE == PLAIN) ? a.n_items_host : (int64_t)*a.n_items_dev;

@@ -585,6 +585,8 @@ struct IntArgs {
     int* unfinished;          // BULK: cells left unfinished by this round
     int* rounds;              // BULK: number of rounds that passed the gate
     const int* gate;          // BULK round > 0: previous round's unfinished count
+    const int* gate_prev;     // BULK round > 0: the count one round earlier (decay gate)
+    double keep;              // stop the rounds once a round keeps more than keep of its cells
     int nstar;
     uint8_t* flag;            // per slot: 0 fresh, 1 saved, 2 done
     SaveArea sv;
@@ -607,6 +609,7 @@ __global__ void __launch_bounds__(64) k_integrate(const Params<M>* __restrict__ 
         const int nact = *a.n_items_dev;
         if (nact == 0) return;
         if (a.gate && *a.gate <= a.nstar) return;
+        if (a.gate_prev && (double)*a.gate > a.keep * (double)*a.gate_prev) return;
         if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(a.rounds, 1);
     }
     const int64_t n_items = (MODE == PLAIN) ? a.n_items_host : (int64_t)*a.n_items_dev;

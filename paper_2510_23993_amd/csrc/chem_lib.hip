@@ -55,6 +55,7 @@ struct Options {
     int group = -1;   // lanes per cell: 0 = compiled one-lane kernel, 4..64 = cooperative, -1 = auto
     int surrogate = 0;        // 1 = surrogate pass before the implicit integration
     double surr_rtol = 1e-6;  // relative tolerance of the surrogate's consistency check
+    double round_decay = 0.0; // stop the bulk rounds once a round retires less than this fraction of its cells
     int method = 0;           // 0 = variable-order BDF, 1 = the explicit first-order scheme
     double explicit_frac = 0.01;  // explicit scheme: largest relative change of a mass fraction per step
     bool operator==(const Options& o) const { return !memcmp(this, &o, sizeof(Options)); }
@@ -336,6 +337,8 @@ int pipeline_k(chem_ctx_s* c, int64_t total, int nbox, double rtol, double atol)
         b.queue = I + I_Q + r;
         b.unfinished = I + I_UNF + r;
         b.gate = r == 0 ? I + I_NACT : I + I_UNF + r - 1;
+        b.gate_prev = r == 0 ? nullptr : (r == 1 ? I + I_NACT : I + I_UNF + r - 2);
+        b.keep = 1.0 - o.round_decay;
         b.kmax = o.kmax_bulk;
         hipLaunchKernelGGL((k_integrate<K, BULK>), dim3(grid), dim3(64), 0, s, PK, b);
     }
@@ -678,6 +681,8 @@ int pipeline_coop(chem_ctx_s* c, int G, int64_t total, int nbox, double rtol, do
         b.queue = I + I_Q + r;
         b.unfinished = I + I_UNF + r;
         b.gate = r == 0 ? I + I_NACT : I + I_UNF + r - 1;
+        b.gate_prev = r == 0 ? nullptr : (r == 1 ? I + I_NACT : I + I_UNF + r - 2);
+        b.keep = 1.0 - o.round_decay;
         b.kmax = o.kmax_bulk;
         rc = launch_coop(c, G, BULK, grid, b, lds);
         if (rc) return rc;
@@ -1075,6 +1080,7 @@ int chem_set_option(chem_ctx_t c, const char* key, double v) {
         if (v == 1 && !c->s_loaded) return fail(CHEM_E_STATE, "no surrogate loaded");
         o.surrogate = (int)v;
     } else if (k == "surr_rtol" && in(1e-12, 1.0)) o.surr_rtol = v;
+    else if (k == "round_decay" && in(0.0, 0.99)) o.round_decay = v;
     else if (k == "method" && (v == 0 || v == 1)) {
         if (v == 1 && !c->m->ops) return fail(CHEM_E_INVAL, "the explicit scheme needs a compiled mechanism");
         o.method = (int)v;
@@ -1102,6 +1108,7 @@ int chem_get_option(chem_ctx_t c, const char* key, double* v) {
     else if (k == "group") *v = o.group;
     else if (k == "surrogate") *v = o.surrogate;
     else if (k == "surr_rtol") *v = o.surr_rtol;
+    else if (k == "round_decay") *v = o.round_decay;
     else if (k == "method") *v = o.method;
     else if (k == "explicit_frac") *v = o.explicit_frac;
     else return fail(CHEM_E_INVAL, "unknown option: " + k);

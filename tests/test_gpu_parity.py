@@ -146,6 +146,7 @@ def test_bulk_sparse_bitwise_equals_plain(chem, mech, m9, group):
     ref = None
     for opts in ({"algorithm": 0}, {"algorithm": 1, "nactive_star": 0, "kmax_bulk": 3},
                  {"algorithm": 1, "nactive_star": 500, "kmax_bulk": 5},
+                 {"algorithm": 1, "nactive_star": 0, "kmax_bulk": 2, "round_decay": 0.5},
                  {"algorithm": 1, "max_rounds": 0}):
         ctx = chem.Context(mech, t_react_min=0.0, group=group, **opts)
         Yg, Tg, st, stats = run_gpu(ctx, rho, e, c.Y, c.T, c.dt, RTOL_C1, ATOL_C1)
@@ -204,3 +205,20 @@ def test_repeat_runs_bitwise_identical(chem, mech, m9, group):
     a = run_gpu(ctx, rho, e, c.Y, c.T, c.dt, RTOL_C1, ATOL_C1)
     b = run_gpu(ctx, rho, e, c.Y, c.T, c.dt, RTOL_C1, ATOL_C1)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_round_decay_gate_stops_rounds_early(chem, mech, m9):
+    # with N* = 0 and 2 steps per round the rounds run until the limit; the
+    # decay gate stops them once a round retires under half of its cells
+    c = fields.c2_field(64, 64, 4, x_scale=1.0)
+    rho, e = oracle_inputs(m9, c)
+    out = []
+    for decay in (0.0, 0.5):
+        ctx = chem.Context(mech, t_react_min=0.0, group=0, nactive_star=0, kmax_bulk=2, max_rounds=24,
+                           round_decay=decay)
+        Yg, Tg, st, stats = run_gpu(ctx, rho, e, c.Y, c.T, c.dt, RTOL_C1, ATOL_C1)
+        assert np.all(st == 0)
+        out.append((stats["n_bulk_rounds"], Yg, Tg))
+    print(f"bulk rounds: {out[0][0]} without the decay gate, {out[1][0]} with it")
+    assert out[1][0] < out[0][0]
+    assert np.array_equal(out[0][1], out[1][1]) and np.array_equal(out[0][2], out[1][2])
