@@ -125,8 +125,9 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="detonation workload: skip chem_autotune")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; the chemistry step "
-                          "shards by cells with no exchange, see DESIGN.md for the multi-GPU design",
+        print(json.dumps({"error": "this benchmark runs on one GPU only: the chemistry step shards "
+                          "by cells with no exchange inside it, so each GPU's work is this "
+                          "single-GPU workload on its share of the cells",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
