@@ -76,3 +76,25 @@ def test_throughput_at_fixed_error(setup):
     print(f"fastest within budget: {'fp32x' if best[0] else 'fp64'} at rtol {best[1]:.0e}, {best[2]:.2f} ms "
           f"({fp64_default[2] / best[2]:.2f}x the FP64 path at rtol 1e-8)")
     assert fp64_default[5]
+
+
+def test_bench_configuration_sample(setup):
+    """The whole 2,097,152-cell field in the benchmark's launch configuration
+    (the options its autotuner picks: one lane per cell, 24 bulk-round
+    launches of 20 steps, N* = 1e5) at its tolerances (rtol 1e-8, atol
+    1e-14): the 400 sampled hot cells against the oracle at tight tolerance,
+    relative bound where the relative tolerance dominates (Y > 1e-6),
+    temperature everywhere."""
+    import torch
+    chem, mech, cells, T0, Y0, rho, e, idx, Yr, Tr = setup
+    ctx = chem.Context(mech, group=0, max_rounds=24, nactive_star=100000, kmax_bulk=20)
+    Y, T = Y0.clone(), T0.clone()
+    status = torch.zeros(T.numel(), dtype=torch.uint8, device="cuda")
+    st = ctx.integrate(rho, e, Y, T, cells.dt, 1e-8, 1e-14, status=status)
+    assert st["rc"] == 0 and int(status.max()) <= chem.ST_SKIPPED
+    Yg, Tg = host(Y)[:, idx], host(T)[idx]
+    dom = Yr > 1e-14 / 1e-8
+    rel = float(np.where(dom, np.abs(Yg - Yr) / np.where(dom, Yr, 1.0), 0.0).max())
+    dT = float(np.abs(Tg - Tr).max())
+    print(f"bench configuration ({st['t_total_ms']:.1f} ms): max rel (Y > 1e-6) {rel:.2e}, max |dT| {dT:.2e} K")
+    assert rel <= 1e-6 and dT <= 1e-3
