@@ -782,7 +782,7 @@ __global__ void __launch_bounds__(64) k_integrate(const Params<M>* __restrict__ 
 // (Eq. 5) and h the largest step for which no mass fraction changes by more
 // than frac of max(|Y_k|, y_floor); T follows from the fixed e by Newton
 // after every step (Alg. 2); the last step ends exactly at dt.  One lane per
-// cell over the compacted active list.
+// cell over the compacted active list, refilled from a device queue.
 struct ExpArgs {
     const DevBox* boxes;
     int nbox;
@@ -790,6 +790,7 @@ struct ExpArgs {
     const int* active_ids;
     const int* n_items_dev;
     const uint8_t* flag;      // per slot: 2 = taken by the surrogate pass
+    int* queue;               // refill counter (zero at launch)
     int kmax;
     double frac, y_floor;
     Counters* ctr;
@@ -800,25 +801,53 @@ __global__ void __launch_bounds__(64) k_explicit(const Params<M>* __restrict__ P
     constexpr int N = M::N, NS = M::NS;
     const Params<M>& P = *Pp;
     const int n = *a.n_items_dev;
+    const int lane = threadIdx.x;
     unsigned long long steps = 0, max_steps = 0, incomplete = 0;
-    for (int s = blockIdx.x * 64 + threadIdx.x; s < n; s += gridDim.x * 64) {
-        if (a.flag[s] == 2) continue;
-        const int64_t g = a.active_ids[s];
-        const DevBox& B = a.boxes[find_box(a.boxes, a.nbox, g)];
-        const int64_t i = g - B.off;
-        const double rho = B.rho[i], e0 = B.e[i], dt = B.dt;
-        double y[N];
-#pragma unroll
-        for (int k = 0; k < NS; k++) y[k] = B.Y[k * B.ldY + i];
-        y[NS] = B.T[i];   // from the screen's inversion of e
-        double t = 0.0;
-        int k = 0;
-        uint8_t st = ST_DONE;
+    // one step per lane and iteration; a lane whose cell is done takes the
+    // next one from the queue, so long and short cells mix within a wave
+    int cur = -1, k = 0;
+    bool exhausted = false;
+    int64_t g = 0, i = 0;
+    const DevBox* B = nullptr;
+    double y[N], rho = 0.0, e0 = 0.0, dt = 0.0, t = 0.0;
+    for (;;) {
         for (;;) {
-            if (k >= a.kmax) {
-                st = ST_KMAX;
-                break;
+            const bool need = cur < 0 && !exhausted;
+            const unsigned long long m = wave_ballot(need);
+            if (!m) break;
+            const int cnt = __popcll(m);
+            const int leader = __ffsll((long long)m) - 1;
+            int base = 0;
+            if (lane == leader) base = atomicAdd(a.queue, cnt);
+            base = __shfl(base, leader);
+            if (need) {
+                const int my = base + __popcll(m & ((1ull << lane) - 1ull));
+                if (my < n) {
+                    if (a.flag[my] != 2) cur = my;
+                } else {
+                    exhausted = true;
+                }
             }
+        }
+        if (wave_ballot(cur >= 0) == 0) break;
+        if (cur < 0) continue;
+        if (k == 0 && t == 0.0) {   // a cell was just taken: load it
+            g = a.active_ids[cur];
+            B = &a.boxes[find_box(a.boxes, a.nbox, g)];
+            i = g - B->off;
+            rho = B->rho[i];
+            e0 = B->e[i];
+            dt = B->dt;
+#pragma unroll
+            for (int q = 0; q < NS; q++) y[q] = B->Y[q * B->ldY + i];
+            y[NS] = B->T[i];   // from the screen's inversion of e
+        }
+        uint8_t st = ST_DONE;
+        bool done = false;
+        if (k >= a.kmax) {
+            st = ST_KMAX;
+            done = true;
+        } else {
             double f[N];
             rhs(P, rho, y, f);
             double h = dt - t;
@@ -833,27 +862,33 @@ __global__ void __launch_bounds__(64) k_explicit(const Params<M>* __restrict__ P
             double Tn;
             if (!T_from_e(P, e0, y, y[NS], Tn)) {
                 st = ST_TINV;
-                break;
+                done = true;
+            } else {
+                y[NS] = Tn;
+                done = last;
             }
-            y[NS] = Tn;
-            if (last) break;
         }
+        if (done) {
 #pragma unroll
-        for (int q = 0; q < NS; q++) B.Y[q * B.ldY + i] = y[q];
-        B.T[i] = y[NS];
-        const uint8_t fin = (st == ST_DONE && a.st_int[g] == ST_SURR_REJ) ? (uint8_t)ST_SURR_REJ : st;
-        a.st_int[g] = fin;
-        if (B.status) B.status[i] = fin;
-        steps += k;
-        max_steps = max(max_steps, (unsigned long long)k);
-        if (st != ST_DONE) incomplete++;
+            for (int q = 0; q < NS; q++) B->Y[q * B->ldY + i] = y[q];
+            B->T[i] = y[NS];
+            const uint8_t fin = (st == ST_DONE && a.st_int[g] == ST_SURR_REJ) ? (uint8_t)ST_SURR_REJ : st;
+            a.st_int[g] = fin;
+            if (B->status) B->status[i] = fin;
+            steps += k;
+            max_steps = max(max_steps, (unsigned long long)k);
+            if (st != ST_DONE) incomplete++;
+            cur = -1;
+            k = 0;
+            t = 0.0;
+        }
     }
     for (int o = 32; o >= 1; o >>= 1) {
         steps += __shfl_xor(steps, o);
         incomplete += __shfl_xor(incomplete, o);
         max_steps = max(max_steps, (unsigned long long)__shfl_xor(max_steps, o));
     }
-    if (threadIdx.x == 0) {
+    if (lane == 0) {
         Counters* ct = a.ctr;
         atomicAdd(&ct->steps, steps);
         atomicAdd(&ct->attempts, steps);

@@ -319,6 +319,7 @@ int pipeline_k(chem_ctx_s* c, int64_t total, int nbox, double rtol, double atol)
         x.active_ids = c->active.as<int>();
         x.n_items_dev = I + I_NACT;
         x.flag = c->flag.as<uint8_t>();
+        x.queue = I + I_Q + RMAX + 1;   // a slot no bulk round or sparse phase uses
         x.kmax = o.kmax_sparse;
         x.frac = o.explicit_frac;
         x.y_floor = EXPLICIT_Y_FLOOR;
