@@ -35,10 +35,10 @@ METRIC = "chemistry cell-steps/s, plain FP64 vs batched/mixed/surrogate at fixed
 # Valid only for the kernel sources they were taken on (hash below) and
 # these options.
 TRAFFIC_PMC = {
-    "src_sha1": "83c536bad08d7ce2de0c99a76c313950ede53ff0",
+    "src_sha1": "4865819382cd8b249a2c0f5fbf69e4bf2c7d4577",
     "options": {"group": 0.0, "max_rounds": 24.0, "nactive_star": 100000.0, "kmax_bulk": 20.0},
-    "fetch_kib": 1.85962e7 / 3, "fetch_factor": 2.0,
-    "write_kib": 3.80862e7 / 3, "write_factor": 1.0,
+    "fetch_kib": 1.85639e7 / 3, "fetch_factor": 2.0,
+    "write_kib": 3.80748e7 / 3, "write_factor": 1.0,
 }
 
 
