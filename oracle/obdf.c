@@ -13,6 +13,16 @@
  * solved by modified Newton with M = I - (h/gamma_k) J.  The local error is
  * estimated as d/(k+1).  A change of step size h -> rho h re-expresses the
  * differences of the interpolating polynomial on the new grid.
+ *
+ * Implementation source followed: SciPy's BDF solver
+ * (scipy/integrate/_ivp/bdf.py, BSD-3-Clause licence), with kappa = 0.  The
+ * modified-Newton loop (at most 4 iterations, the convergence-rate test
+ * rate^(4-it)/(1-rate) |dy| against newton_tol = max(10 eps/rtol,
+ * min(0.03, sqrt(rtol)))), the update of the difference array on acceptance
+ * and the order and step selection (safety 0.9, factors clamped to
+ * [0.2, 10]) follow it.  Written here: the re-expression of the differences
+ * on a new grid (rescale), the Jacobian reuse policy, the last-step clamp
+ * onto t1 and the starting step of Hairer, Norsett & Wanner.
  */
 #include "oracle.h"
 

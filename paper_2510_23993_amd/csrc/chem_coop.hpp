@@ -538,6 +538,11 @@ __device__ __forceinline__ void coop_solve(const GL& gl, int l, int base, int n,
 }
 
 // ---------------------------------------------------------------- BDF (group)
+// The same variable-order BDF as the one-lane stepper (Shampine & Reichelt
+// 1997, kappa = 0), with each component's differences in the registers of
+// the lane that owns it.  Newton convergence test, difference update and
+// order selection follow SciPy's BDF (scipy/integrate/_ivp/bdf.py,
+// BSD-3-Clause).
 template <int G, int R>
 struct CLane {
     static constexpr int NC = G * R;

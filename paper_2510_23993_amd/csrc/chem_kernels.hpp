@@ -225,8 +225,10 @@ __global__ void k_eval_rhs(const Params<M>* __restrict__ Pp, int64_t n, const do
 // with M = I - c_lu J (LU in LDS; J and LU refreshed together when the
 // step-size coefficient drifts by more than 30% or Newton fails with a
 // Jacobian from an earlier step), local error d/(k+1), WRMS norm with
-// weights 1/(rtol |y| + atol).  D lives in global memory: D(j, i) at
-// D[(j*N + i) * ld].
+// weights 1/(rtol |y| + atol).  The Newton convergence test, the update of
+// the differences on acceptance and the order selection follow SciPy's BDF
+// implementation (scipy/integrate/_ivp/bdf.py, BSD-3-Clause).  D lives in
+// global memory: D(j, i) at D[(j*N + i) * ld].
 
 __device__ __forceinline__ double gamma_k(int k) {  // sum_{i<=k} 1/i
     double g = 0.0;

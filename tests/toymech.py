@@ -25,7 +25,7 @@ def isomer_AB(A=1e6, Ea=0.0, b=0.0, da7=0.7, reversible=True):
     return Mechanism("isomer", ["X", "N"], sp, rx)
 
 
-def dimer(A=3e12, reversible=False):
+def dimer(A=3e12, reversible=False, b=0.0, Ea=0.0):
     """2A => B with molar internal energies u_B = 2 u_A at every T (so
     h_B/RT = 2 h_A/RT - 1): the reaction releases no heat and T is constant."""
     sp = [const_cp_species("A", {"X": 1}, a6=500.0, a7=3.0, W=20.0),
@@ -33,7 +33,7 @@ def dimer(A=3e12, reversible=False):
           const_cp_species("N2", {"N": 2})]
     sp[1].nasa_low = [6.0, 0, 0, 0, 0, 1000.0, 5.0]
     sp[1].nasa_high = list(sp[1].nasa_low)
-    rx = [Reaction({"A": 2}, {"B": 1}, A=A, b=0.0, Ea=0.0, reversible=reversible)]
+    rx = [Reaction({"A": 2}, {"B": 1}, A=A, b=b, Ea=Ea, reversible=reversible)]
     return Mechanism("dimer", ["X", "N"], sp, rx)
 
 
@@ -47,6 +47,8 @@ def thirdbody_iso(A=5e9, effA=0.0, effB=0.0):
 
 
 def falloff_iso(Ainf=1e7, A0=1e13, troe=None):
+    """A (+M) => B (+M), Lindemann or Troe, temperature-independent k_inf and
+    k0, zero efficiency for A and B (so [M] = C_N2)."""
     m = isomer_AB()
     m.reactions = [Reaction({"A": 1}, {"B": 1}, A=Ainf, b=0.0, Ea=0.0, kind="FALLOFF",
                             reversible=False, efficiencies={"A": 0.0, "B": 0.0},
