@@ -188,7 +188,10 @@ int o_bdf(int n, double t0, double t1, double *y, double rtol, double atol, long
             break;
         }
         int last = 0;
-        if (t + h >= t1) {
+        /* the step reaches t1 when t + h rounds to t1 or beyond, or when h
+         * covers t1 - t: after the clamp below h = t1 - t exactly, and a
+         * retry at that size must land on t1 although t + h may round below */
+        if (t + h >= t1 || h >= t1 - t) {
             double hn = t1 - t;
             rescale(n, k, D, hn / h, tmp);
             h = hn;

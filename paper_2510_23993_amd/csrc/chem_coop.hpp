@@ -624,7 +624,7 @@ __device__ __forceinline__ int cbdf_attempt(const CoopMech& M, const GL& gl, int
     L.n_att++;
     if (!(L.h >= 10.0 * EPS * fabs(L.t))) return SR_FAIL;
     bool last = false;
-    if (L.t + L.h >= L.tend) {
+    if (L.t + L.h >= L.tend || L.h >= L.tend - L.t) {   // rounding of t + h cannot hide the end
         const double hn = L.tend - L.t;
         crescale<G, R>(L, L.k, hn / L.h);
         L.h = hn;

@@ -498,10 +498,13 @@ __device__ __forceinline__ int bdf_attempt(const Params<M>& P, Lane<M>& L, doubl
         }
     }
     if (res == SR_DONE) return res;
-    // the step size of the next attempt, clamped onto t_end
+    // the step size of the next attempt, clamped onto t_end; a step reaches
+    // t_end when t + h rounds to it or when h covers the remaining interval
+    // (after the clamp h = t_end - t exactly, but t + h may round below t_end:
+    // a retry at the same size must still land on t_end)
     double hn = L.h * fac;
     if (!(hn >= 10.0 * EPS * fabs(L.t))) return SR_FAIL;
-    L.last = L.t + hn >= L.tend;
+    L.last = L.t + hn >= L.tend || hn >= L.tend - L.t;
     if (L.last) {
         fac = (L.tend - L.t) / L.h;
         hn = L.tend - L.t;
@@ -562,7 +565,7 @@ __device__ __forceinline__ void bdf_init(const Params<M>& P, Lane<M>& L, double*
     L.lu_ok = false;
     L.jac_fresh = false;
     L.c_lu = 0.0;
-    L.last = L.h >= L.tend;
+    L.last = L.h >= L.tend;   // t = 0: the first step covers the interval
 }
 
 // ------------------------------------------------------- integration kernel

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -35,6 +36,16 @@ int fail(int code, const std::string& msg) {
     do {                                                                                  \
         hipError_t e_ = (x);                                                              \
         if (e_ != hipSuccess) return fail(CHEM_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// every kernel launch is checked where it is enqueued, so a failed launch is
+// reported with its line rather than by a later call
+#define LAUNCHED()                                                                        \
+    do {                                                                                  \
+        hipError_t e_ = hipGetLastError();                                                \
+        if (e_ != hipSuccess)                                                             \
+            return fail(CHEM_E_HIP, std::string("kernel launch at chem_lib.hip:") + std::to_string(__LINE__) + \
+                                        ": " + hipGetErrorString(e_));                    \
     } while (0)
 
 constexpr int RMAX = 64;  // most bulk-round launches per pipeline
@@ -272,12 +283,12 @@ int pipeline_k(chem_ctx_s* c, int64_t total, int nbox, double rtol, double atol)
     int* I = c->ints.as<int>();
     Counters* ctr = c->ctr.as<Counters>();
     const int64_t nb = std::max<int64_t>(1, (total + 255) / 256);
-    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, s, I, (int64_t)I_COUNT, 0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, s, I, (int64_t)I_COUNT, 0); LAUNCHED();
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, (unsigned long long*)ctr,
-                       (int64_t)(2 * sizeof(Counters) / 8));
+                       (int64_t)(2 * sizeof(Counters) / 8)); LAUNCHED();
     const double tmin = o.algorithm == 1 ? o.t_react_min : -1.0;
     hipLaunchKernelGGL((k_screen<M>), dim3(nb), dim3(256), 0, s, P, db, nbox, total, tmin,
-                       c->st_int.as<uint8_t>(), c->bcnt.as<int>());
+                       c->st_int.as<uint8_t>(), c->bcnt.as<int>()); LAUNCHED();
     IntArgs a{};
     a.boxes = db;
     a.nbox = nbox;
@@ -297,14 +308,14 @@ int pipeline_k(chem_ctx_s* c, int64_t total, int nbox, double rtol, double atol)
         a.kmax = o.kmax_sparse;
         mark(c, 2);
         constexpr int LW = lanes_per_wave<K>();
-        hipLaunchKernelGGL((k_integrate<K, PLAIN>), dim3((total + LW - 1) / LW), dim3(64), 0, s, PK, a);
+        hipLaunchKernelGGL((k_integrate<K, PLAIN>), dim3((total + LW - 1) / LW), dim3(64), 0, s, PK, a); LAUNCHED();
         return 0;
     }
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, c->bcnt.as<int>(), (int)nb, c->boff.as<int>(), I + I_NACT);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, c->bcnt.as<int>(), (int)nb, c->boff.as<int>(), I + I_NACT); LAUNCHED();
     hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(256), 0, s, c->st_int.as<uint8_t>(), total, c->boff.as<int>(),
-                       c->active.as<int>());
+                       c->active.as<int>()); LAUNCHED();
     hipLaunchKernelGGL(k_fill_u8, dim3(std::min<int64_t>(nb, 4096)), dim3(256), 0, s, c->flag.as<uint8_t>(),
-                       std::max<int64_t>(total, 1), (uint8_t)0);
+                       std::max<int64_t>(total, 1), (uint8_t)0); LAUNCHED();
     if (o.surrogate) {
         mark(c, 3);
         rc = c->m->ops->surrogate(c, total, nbox, atol);
@@ -327,7 +338,7 @@ int pipeline_k(chem_ctx_s* c, int64_t total, int nbox, double rtol, double atol)
         mark(c, 0);
         mark(c, 1);
         mark(c, 2);
-        hipLaunchKernelGGL((k_explicit<K>), dim3(grid), dim3(64), 0, s, PK, x);
+        hipLaunchKernelGGL((k_explicit<K>), dim3(grid), dim3(64), 0, s, PK, x); LAUNCHED();
         return 0;
     }
     const int rounds = std::min(o.max_rounds, RMAX);
@@ -341,21 +352,21 @@ int pipeline_k(chem_ctx_s* c, int64_t total, int nbox, double rtol, double atol)
         b.gate_prev = r == 0 ? nullptr : (r == 1 ? I + I_NACT : I + I_UNF + r - 2);
         b.keep = 1.0 - o.round_decay;
         b.kmax = o.kmax_bulk;
-        hipLaunchKernelGGL((k_integrate<K, BULK>), dim3(grid), dim3(64), 0, s, PK, b);
+        hipLaunchKernelGGL((k_integrate<K, BULK>), dim3(grid), dim3(64), 0, s, PK, b); LAUNCHED();
     }
     mark(c, 1);
     hipLaunchKernelGGL(k_count_unfinished, dim3(nb), dim3(256), 0, s, c->flag.as<uint8_t>(), I + I_NACT,
-                       c->bcnt.as<int>());
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, c->bcnt.as<int>(), (int)nb, c->boff.as<int>(), I + I_NSP);
+                       c->bcnt.as<int>()); LAUNCHED();
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, c->bcnt.as<int>(), (int)nb, c->boff.as<int>(), I + I_NSP); LAUNCHED();
     hipLaunchKernelGGL(k_scatter_unfinished, dim3(nb), dim3(256), 0, s, c->flag.as<uint8_t>(), I + I_NACT,
-                       c->boff.as<int>(), c->sparse.as<int>());
+                       c->boff.as<int>(), c->sparse.as<int>()); LAUNCHED();
     IntArgs sp = a;
     sp.items = c->sparse.as<int>();
     sp.n_items_dev = I + I_NSP;
     sp.queue = I + I_Q + RMAX;
     sp.kmax = o.kmax_sparse;
     mark(c, 2);
-    hipLaunchKernelGGL((k_integrate<K, SPARSE>), dim3(grid), dim3(64), 0, s, PK, sp);
+    hipLaunchKernelGGL((k_integrate<K, SPARSE>), dim3(grid), dim3(64), 0, s, PK, sp); LAUNCHED();
     return 0;
 }
 
@@ -534,15 +545,52 @@ int coop_lds_bytes(const chem_mech_s* m, int G) {
     return 8 * ((64 / G) * (gl + n * n));
 }
 
+// The dynamic-LDS limit of every cooperative kernel is raised once per
+// device to the device's opt-in maximum (a limit, not an allocation: each
+// launch still asks for exactly its own size), so no call can be left with
+// the smaller limit of an earlier call.  std::call_once makes it safe for
+// contexts created concurrently.
+constexpr int MAX_DEVICES = 64;
+std::once_flag g_lds_once[MAX_DEVICES];
+int g_lds_max[MAX_DEVICES];
+
+int coop_lds_init(int device) {
+    if (device < 0 || device >= MAX_DEVICES) return fail(CHEM_E_INVAL, "device index out of range");
+    hipError_t err = hipSuccess;
+    std::call_once(g_lds_once[device], [&] {
+        int v = 0;
+        err = hipDeviceGetAttribute(&v, hipDeviceAttributeSharedMemPerBlockOptin, device);
+        if (err != hipSuccess || v <= 0) err = hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, device);
+        if (err != hipSuccess) return;
+        auto set = [&](const void* f) {
+            const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, v);
+            if (e != hipSuccess && err == hipSuccess) err = e;
+        };
+#define X(g, r)                                                  \
+        set((const void*)k_integrate_coop<g, r, PLAIN>);         \
+        set((const void*)k_integrate_coop<g, r, BULK>);          \
+        set((const void*)k_integrate_coop<g, r, SPARSE>);        \
+        set((const void*)k_eval_coop<g, r>);
+        CHEM_COOP_SCHEDULES(X)
+#undef X
+        g_lds_max[device] = v;
+    });
+    if (err != hipSuccess) return fail(CHEM_E_HIP, std::string("LDS limit of the cooperative kernels: ") + hipGetErrorString(err));
+    if (g_lds_max[device] <= 0) return fail(CHEM_E_HIP, "LDS limit of the cooperative kernels was not set");
+    return 0;
+}
+
+int check_coop_lds(const chem_ctx_s* c, int lds) {
+    if (lds > g_lds_max[c->device])
+        return fail(CHEM_E_MECH, "the cooperative schedule needs " + std::to_string(lds) + " B of LDS per workgroup, more than the device's " +
+                                     std::to_string(g_lds_max[c->device]) + " B: use more lanes per cell");
+    return 0;
+}
+
 template <int G, int R, int MODE>
 int launch_coop_one(chem_ctx_s* c, int64_t grid, const CoopArgs& a, int lds) {
-    static bool attr = false;
-    if (!attr) {
-        (void)hipFuncSetAttribute((const void*)k_integrate_coop<G, R, MODE>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-        attr = true;
-    }
-    hipLaunchKernelGGL((k_integrate_coop<G, R, MODE>), dim3(grid), dim3(64), lds, c->stream, a);
+    if (int rc = check_coop_lds(c, lds)) return rc;
+    hipLaunchKernelGGL((k_integrate_coop<G, R, MODE>), dim3(grid), dim3(64), lds, c->stream, a); LAUNCHED();
     return 0;
 }
 
@@ -566,8 +614,6 @@ int coop_blocks_per_cu(chem_ctx_s* c, int G) {
     switch (G) {
 #define X(g, r)                                                                                       \
     case g:                                                                                           \
-        (void)hipFuncSetAttribute((const void*)k_integrate_coop<g, r, SPARSE>,                        \
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds);                  \
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_integrate_coop<g, r, SPARSE>, 64, lds); \
         break;
         CHEM_COOP_SCHEDULES(X)
@@ -635,12 +681,12 @@ int pipeline_coop(chem_ctx_s* c, int G, int64_t total, int nbox, double rtol, do
     int* I = c->ints.as<int>();
     Counters* ctr = c->ctr.as<Counters>();
     const int64_t nb = std::max<int64_t>(1, (total + 255) / 256);
-    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, s, I, (int64_t)I_COUNT, 0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, s, I, (int64_t)I_COUNT, 0); LAUNCHED();
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, (unsigned long long*)ctr,
-                       (int64_t)(2 * sizeof(Counters) / 8));
+                       (int64_t)(2 * sizeof(Counters) / 8)); LAUNCHED();
     const double tmin = o.algorithm == 1 ? o.t_react_min : -1.0;
     hipLaunchKernelGGL(k_screen_coop, dim3(nb), dim3(256), 0, s, c->m->cm, db, nbox, total, tmin,
-                       c->st_int.as<uint8_t>(), c->bcnt.as<int>());
+                       c->st_int.as<uint8_t>(), c->bcnt.as<int>()); LAUNCHED();
     CoopArgs a{};
     a.M = c->m->cm;
     a.M.prec = o.precision;
@@ -663,11 +709,11 @@ int pipeline_coop(chem_ctx_s* c, int G, int64_t total, int nbox, double rtol, do
         mark(c, 2);
         return launch_coop(c, G, PLAIN, (total + ngrp - 1) / ngrp, a, lds);
     }
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, c->bcnt.as<int>(), (int)nb, c->boff.as<int>(), I + I_NACT);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, c->bcnt.as<int>(), (int)nb, c->boff.as<int>(), I + I_NACT); LAUNCHED();
     hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(256), 0, s, c->st_int.as<uint8_t>(), total, c->boff.as<int>(),
-                       c->active.as<int>());
+                       c->active.as<int>()); LAUNCHED();
     hipLaunchKernelGGL(k_fill_u8, dim3(std::min<int64_t>(nb, 4096)), dim3(256), 0, s, c->flag.as<uint8_t>(),
-                       std::max<int64_t>(total, 1), (uint8_t)0);
+                       std::max<int64_t>(total, 1), (uint8_t)0); LAUNCHED();
     if (o.surrogate) {
         mark(c, 3);
         rc = c->m->ops->surrogate(c, total, nbox, atol);
@@ -690,10 +736,10 @@ int pipeline_coop(chem_ctx_s* c, int G, int64_t total, int nbox, double rtol, do
     }
     mark(c, 1);
     hipLaunchKernelGGL(k_count_unfinished, dim3(nb), dim3(256), 0, s, c->flag.as<uint8_t>(), I + I_NACT,
-                       c->bcnt.as<int>());
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, c->bcnt.as<int>(), (int)nb, c->boff.as<int>(), I + I_NSP);
+                       c->bcnt.as<int>()); LAUNCHED();
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, c->bcnt.as<int>(), (int)nb, c->boff.as<int>(), I + I_NSP); LAUNCHED();
     hipLaunchKernelGGL(k_scatter_unfinished, dim3(nb), dim3(256), 0, s, c->flag.as<uint8_t>(), I + I_NACT,
-                       c->boff.as<int>(), c->sparse.as<int>());
+                       c->boff.as<int>(), c->sparse.as<int>()); LAUNCHED();
     CoopArgs sp = a;
     sp.items = c->sparse.as<int>();
     sp.n_items_dev = I + I_NSP;
@@ -714,7 +760,7 @@ int eval_coop_t(chem_ctx_s* c, int64_t n, const double* rho, const double* y, do
     const int NC = G * R, ngrp = 64 / G;
     const int lds = coop_lds_bytes(c->m, G);
     const int gls = group_lds_doubles(c->m->hm.ns, (int)c->m->hm.rx.size(), NC);
-    (void)hipFuncSetAttribute((const void*)k_eval_coop<G, R>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (int rc = check_coop_lds(c, lds)) return rc;
     CoopMech cm = c->m->cm;
     cm.prec = c->opt.precision;
     hipLaunchKernelGGL((k_eval_coop<G, R>), dim3((n + ngrp - 1) / ngrp), dim3(64), lds, c->stream, cm,
@@ -779,13 +825,13 @@ int surrogate_pass(chem_ctx_s* c, int64_t total, int nbox, double atol) {
         const mlp::MlpDev net{c->s_params.as<float>(), bf, bf + mlp::NW2H, bf + mlp::NW2H + mlp::NW3H};
         const int64_t g1 = std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, (int64_t)c->ncu * 8));
         const int64_t g2 = std::max<int64_t>(1, std::min<int64_t>((total + 63) / 64, (int64_t)c->ncu * 16));
-        hipLaunchKernelGGL((k_surr_prep<M>), dim3(g1), dim3(256), 0, s, P, tb, db, nbox, ids, nact, cap, X, ok);
+        hipLaunchKernelGGL((k_surr_prep<M>), dim3(g1), dim3(256), 0, s, P, tb, db, nbox, ids, nact, cap, X, ok); LAUNCHED();
         for (int part = 0; part < 2; part++) {
             rc = mlp::launch_infer(s, net, 0, nact, total, X + part * cap * mlp::NIN, O + part * cap * mlp::NOUT, c->ncu);
             if (rc) return rc;
         }
         hipLaunchKernelGGL((k_surr_mid<M>), dim3(g2), dim3(64), 0, s, P, tb, db, nbox, ids, nact, cap, O, X,
-                           c->s_yh.as<double>(), ok, atol);
+                           c->s_yh.as<double>(), ok, atol); LAUNCHED();
         rc = mlp::launch_infer(s, net, 0, nact, total, X + 2 * cap * mlp::NIN, O + 2 * cap * mlp::NOUT, c->ncu);
         if (rc) return rc;
         hipLaunchKernelGGL((k_surr_accept<M>), dim3(g2), dim3(64), 0, s, P, tb, db, nbox, ids, nact, cap, O,
@@ -1037,6 +1083,7 @@ int chem_ctx_create(chem_mech_t m, int device, void* stream, chem_ctx_t* out) {
     hipDeviceProp_t prop;
     HIPCHK(hipGetDeviceProperties(&prop, device));
     c->ncu = prop.multiProcessorCount;
+    if (int rc = coop_lds_init(device)) return rc;
     for (auto& e : c->ev_copy) {
         HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         HIPCHK(hipEventRecord(e, c->stream));
