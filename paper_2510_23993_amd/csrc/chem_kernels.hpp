@@ -303,6 +303,24 @@ __device__ __forceinline__ void rescale(double* D, int64_t ld, int k, double r) 
 
 enum StepResult { SR_RETRY = 0, SR_ACCEPT = 1, SR_DONE = 2, SR_FAIL = 3 };
 
+// Step size hn = h fac of the next attempt, clamped onto t_end (fac is then
+// the clamped ratio).  A step reaches t_end when t + hn rounds to it or when
+// hn covers the remaining interval: after a clamp h = t_end - t exactly, but
+// t + h may round below t_end, and a retry at that size must still land on
+// t_end.  Returns false when hn is below the resolution of t.
+template <class M>
+__device__ __forceinline__ bool next_step(Lane<M>& L, double& fac, double& hn) {
+    constexpr double EPS = 2.220446049250313e-16;
+    hn = L.h * fac;
+    if (!(hn >= 10.0 * EPS * fabs(L.t))) return false;
+    L.last = L.t + hn >= L.tend || hn >= L.tend - L.t;
+    if (L.last) {
+        fac = (L.tend - L.t) / L.h;
+        hn = L.tend - L.t;
+    }
+    return true;
+}
+
 // Every change of step size (rejections, order and step selection, the
 // clamp of the last step onto t_end) goes through one rescale of D at the
 // end of the attempt: the ratios of successive changes multiply, since each
@@ -498,18 +516,9 @@ __device__ __forceinline__ int bdf_attempt(const Params<M>& P, Lane<M>& L, doubl
         }
     }
     if (res == SR_DONE) return res;
-    // the step size of the next attempt, clamped onto t_end; a step reaches
-    // t_end when t + h rounds to it or when h covers the remaining interval
-    // (after the clamp h = t_end - t exactly, but t + h may round below t_end:
-    // a retry at the same size must still land on t_end)
-    double hn = L.h * fac;
-    if (!(hn >= 10.0 * EPS * fabs(L.t))) return SR_FAIL;
-    L.last = L.t + hn >= L.tend || hn >= L.tend - L.t;
-    if (L.last) {
-        fac = (L.tend - L.t) / L.h;
-        hn = L.tend - L.t;
-        resc = true;
-    }
+    double hn;
+    if (!next_step(L, fac, hn)) return SR_FAIL;
+    resc = resc || L.last;
     if (resc) {
         rescale<N>(D, ld, L.k, fac);
         L.h = hn;

@@ -15,6 +15,7 @@
 
 #include "chem.h"
 #include "chem_host_mech.hpp"
+#include "chem_params.hpp"
 #include "chem_coop.hpp"
 #include "chem_kernels.hpp"
 #include "chem_mlp.hpp"
@@ -158,39 +159,7 @@ template <class M>
 int upload_params(const HostMech& h, void** out) {
     if (h.ns != M::NS || (int)h.rx.size() != M::NR) return fail(CHEM_E_MECH, "size mismatch");
     auto P = std::make_unique<Params<M>>();
-    memset(P.get(), 0, sizeof(Params<M>));
-    for (int k = 0; k < M::NS; k++) {
-        P->W[k] = h.W[k];
-        P->invW[k] = 1.0 / h.W[k];
-        P->Tmid[k] = h.Tmid[k];
-        const double* lo = &h.alo[7 * k];
-        const double* hi = &h.ahi[7 * k];
-        const double* src[2] = {lo, hi};
-        double(*H[2])[6] = {P->hlo, P->hhi};
-        double(*S[2])[6] = {P->slo, P->shi};
-        double(*Cc[2])[5] = {P->clo, P->chi};
-        for (int r = 0; r < 2; r++) {
-            const double* a = src[r];
-            const double hc[6] = {a[0], a[1] / 2, a[2] / 3, a[3] / 4, a[4] / 5, a[5]};
-            const double sc[6] = {a[0], a[1], a[2] / 2, a[3] / 3, a[4] / 4, a[6]};
-            for (int q = 0; q < 6; q++) {
-                H[r][k][q] = hc[q];
-                S[r][k][q] = sc[q];
-            }
-            for (int q = 0; q < 5; q++) Cc[r][k][q] = a[q];
-        }
-    }
-    for (int j = 0; j < M::NR; j++) {
-        const HostReaction& r = h.rx[j];
-        P->lnA[j] = std::log(r.A);
-        P->b[j] = r.b;
-        P->EaR[j] = r.Ea / RGAS;
-        P->lnA0[j] = r.type == 2 ? std::log(r.A0) : 0.0;
-        P->b0[j] = r.b0;
-        P->Ea0R[j] = r.Ea0 / RGAS;
-        for (int q = 0; q < 4; q++) P->troe[j][q] = r.troe[q];
-        for (int k = 0; k < M::NS; k++) P->eff[j][k] = r.eff[k];
-    }
+    pack_params<M>(h, *P);
     void* d = nullptr;
     HIPCHK(hipMalloc(&d, sizeof(Params<M>)));
     HIPCHK(hipMemcpy(d, P.get(), sizeof(Params<M>), hipMemcpyHostToDevice));
