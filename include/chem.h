@@ -103,6 +103,10 @@ typedef struct {
      * the training envelope, a mass fraction below -10 atol, temperature
      * mismatch, one-step vs two-step disagreement */
     int64_t surr_reject[4];
+    /* chem_strang_step: device time of the two flow half steps, and cells
+     * whose temperature inversion failed in the flow's primitive pass */
+    double t_flow_ms;
+    int64_t flow_bad_cells;
 } chem_stats;
 
 /* One AMR box (a separately allocated grid): device pointers, column-major
@@ -203,6 +207,31 @@ int chem_integrate(chem_ctx_t c, int64_t ncell, const double* rho, const double*
  * work completes.  Same return conventions as chem_integrate. */
 int chem_integrate_boxes(chem_ctx_t c, int nbox, const chem_box* boxes, double rtol, double atol,
                          chem_stats* stats);
+
+/* One step of the minimal one-dimensional compressible flow around the
+ * chemistry (Sec. 2.1: HLLC convective fluxes, second-order SSP Runge-Kutta):
+ * MUSCL reconstruction of (rho, u, p, Y) with the minmod limiter, HLLC with
+ * the direct wave-speed estimates, Heun's SSP-RK2, transmissive ends.
+ *   U   [3 + nspec][ldU] device, in/out, component-major: rho, rho u, rho E,
+ *       rho Y_1 .. rho Y_nspec per cell (E = e + u^2/2, e the chemistry's
+ *       mass-specific internal energy including formation energy)
+ *   T   [ncell] device, in: temperature guess of the Newton inversion of e
+ *       (values outside (100, 6000) K mean none), out: T of the new state
+ *   dx  cell size [m], dt step [s] (the caller keeps dt within the CFL limit)
+ * Compiled mechanisms only (CHEM_E_INVAL otherwise).  Synchronises the
+ * stream; CHEM_E_STATE if a cell's state left the thermo's bracket. */
+int chem_flow_step(chem_ctx_t c, int64_t ncell, double dx, double dt, double* U, int64_t ldU, double* T);
+
+/* One Strang-split reacting step (Sec. 2.1 operator splitting): flow over
+ * dt/2, the chemistry of chem_integrate over dt (constant rho and e per cell,
+ * so only rho Y changes), flow over dt/2.  U, T as chem_flow_step; status
+ * [ncell] or NULL as chem_integrate.  With stats the call synchronises and
+ * also reports the flow half steps' device time (t_flow_ms) next to the
+ * chemistry's phases; without, it is asynchronous.  Returns as
+ * chem_integrate; CHEM_E_STATE if the flow's temperature inversion failed
+ * (stats only). */
+int chem_strang_step(chem_ctx_t c, int64_t ncell, double dx, double dt, double* U, int64_t ldU, double* T,
+                     uint8_t* status, double rtol, double atol, chem_stats* stats);
 
 /* (T, p, Y) -> (rho, e) on the device for ncell cells (ideal gas, NASA-7):
  * a convenience to build reactor inputs from primitive states.  T, p

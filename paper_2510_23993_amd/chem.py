@@ -26,7 +26,8 @@ class chem_stats(C.Structure):
         "lin_solves", "max_steps_cell")] + [(n, C.c_double) for n in (
         "t_total_ms", "t_screen_ms", "t_bulk_ms", "t_sparse_ms")] + [(n, C.c_int64) for n in (
         "bulk_rhs_evals", "bulk_jac_evals", "bulk_lu_facts", "bulk_lin_solves")] + [
-        ("n_surrogate", C.c_int64), ("t_surrogate_ms", C.c_double), ("surr_reject", C.c_int64 * 4)]
+        ("n_surrogate", C.c_int64), ("t_surrogate_ms", C.c_double), ("surr_reject", C.c_int64 * 4),
+        ("t_flow_ms", C.c_double), ("flow_bad_cells", C.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -54,7 +55,8 @@ EXPORTS = ["chem_load_mechanism", "chem_mech_info", "chem_species_name", "chem_f
            "chem_eval_rhs", "chem_synchronize", "chem_last_error", "chem_autotune",
            "chem_mlp_nparams", "chem_mlp_workspace_floats", "chem_mlp_forward", "chem_mlp_backward",
            "chem_mlp_mse", "chem_mlp_adam", "chem_mlp_gather", "chem_mlp_colstats", "chem_mlp_standardize",
-           "chem_mlp_colrange", "chem_surrogate_pairs", "chem_mech_hash"]
+           "chem_mlp_colrange", "chem_surrogate_pairs", "chem_mech_hash",
+           "chem_flow_step", "chem_strang_step"]
 
 
 def lib():
@@ -85,6 +87,8 @@ def lib():
     L.chem_integrate.argtypes = [vp, i64, vp, vp, vp, i64, vp, vp, vp, dbl, dbl, dbl,
                                  C.POINTER(chem_stats)]
     L.chem_integrate_boxes.argtypes = [vp, C.c_int, C.POINTER(chem_box), dbl, dbl, C.POINTER(chem_stats)]
+    L.chem_flow_step.argtypes = [vp, i64, dbl, dbl, vp, i64, vp]
+    L.chem_strang_step.argtypes = [vp, i64, dbl, dbl, vp, i64, vp, vp, dbl, dbl, C.POINTER(chem_stats)]
     L.chem_prepare_state.argtypes = [vp, i64, vp, vp, vp, i64, vp, vp]
     L.chem_eval_rhs.argtypes = [vp, i64, vp, vp, vp, vp]
     L.chem_synchronize.argtypes = [vp]
@@ -208,6 +212,28 @@ class Context:
         rc = _check(lib().chem_integrate(self._h, n, _ptr(rho), _ptr(e), _ptr(Y), n, _ptr(T),
                                          _ptr(mask), _ptr(status), float(dt), float(rtol),
                                          float(atol), C.byref(st) if st is not None else None))
+        if st is None:
+            return None
+        d = st.as_dict()
+        d["rc"] = rc
+        return d
+
+    def flow_step(self, U, T, dx, dt):
+        """One SSP-RK2 step of the 1-D flow: U [3+ns, n], T [n] (in: guess,
+        out: T of the new state); synchronises."""
+        n = T.shape[0]
+        _check_f64("T", T, (n,))
+        _check_f64("U", U, (3 + self.mech.ns, n))
+        _check(lib().chem_flow_step(self._h, n, float(dx), float(dt), _ptr(U), n, _ptr(T)))
+
+    def strang_step(self, U, T, dx, dt, rtol, atol, status=None, stats=True):
+        """Flow dt/2, chemistry dt, flow dt/2 (U, T as flow_step)."""
+        n = T.shape[0]
+        _check_f64("T", T, (n,))
+        _check_f64("U", U, (3 + self.mech.ns, n))
+        st = chem_stats() if stats else None
+        rc = _check(lib().chem_strang_step(self._h, n, float(dx), float(dt), _ptr(U), n, _ptr(T), _ptr(status),
+                                           float(rtol), float(atol), C.byref(st) if st is not None else None))
         if st is None:
             return None
         d = st.as_dict()

@@ -254,37 +254,61 @@ __device__ __forceinline__ void rxn_lnq(const CellEval<M>& E, double lnkf, doubl
     }
 }
 
+// Net rate of progress of reaction j (times [M] for a third-body reaction).
+template <class M, int j>
+__device__ __forceinline__ double rxn_net(const Params<M>& P, const CellEval<M>& E) {
+    RxnK r;
+    rxn_k<M, j>(P, E.lnT, E.invT, E.C, r, false);
+    double lnqf, lnqr, sf, sr;
+    rxn_lnq<M, j>(E, r.lnkf, lnqf, lnqr, sf, sr);
+    double q;
+    if constexpr (M::PREC) {
+        // FP32 exponentials: near equilibrium the net rate is -qf expm1(d)
+        // with the FP64 log ratio d, not a difference of two rounded q's
+        const double Ef = exp32(lnqf);
+        q = sf * Ef;
+        if (M::REV[j]) {
+            const double d = lnqr - lnqf;
+            if (sf == sr && fabs(d) < 0.35) q = -q * expm1_small(d);
+            else q -= sr * exp32(lnqr);
+        }
+    } else {
+        q = sf * exp(lnqf);
+        if (M::REV[j]) q -= sr * exp(lnqr);
+    }
+    if (M::TYPE[j] == RX_TB) q *= r.M;
+    return q;
+}
+
+template <class M, int j>
+__device__ __forceinline__ void rxn_scatter(double q, double* om) {
+#pragma unroll
+    for (int i = 0; i < M::NRE[j]; i++) om[M::RSP[j][i]] -= M::RNU[j][i] * q;
+#pragma unroll
+    for (int i = 0; i < M::NPR[j]; i++) om[M::PSP[j][i]] += M::PNU[j][i] * q;
+}
+
+// Reactions are evaluated CHEM_RXN_GROUP at a time between scheduling
+// barriers: the exp/log sequences of a group are independent and can
+// interleave, while the barriers keep the scheduler from interleaving the
+// whole reaction list (whose live ranges would overflow the register file).
+#ifndef CHEM_RXN_GROUP
+#define CHEM_RXN_GROUP 1
+#endif
+
 template <class M, int j>
 __device__ __forceinline__ void rhs_loop(const Params<M>& P, const CellEval<M>& E, double* om) {
     if constexpr (j < M::NR) {
-        RxnK r;
-        rxn_k<M, j>(P, E.lnT, E.invT, E.C, r, false);
-        double lnqf, lnqr, sf, sr;
-        rxn_lnq<M, j>(E, r.lnkf, lnqf, lnqr, sf, sr);
-        double q;
-        if constexpr (M::PREC) {
-            // FP32 exponentials: near equilibrium the net rate is -qf expm1(d)
-            // with the FP64 log ratio d, not a difference of two rounded q's
-            const double Ef = exp32(lnqf);
-            q = sf * Ef;
-            if (M::REV[j]) {
-                const double d = lnqr - lnqf;
-                if (sf == sr && fabs(d) < 0.35) q = -q * expm1_small(d);
-                else q -= sr * exp32(lnqr);
-            }
-        } else {
-            q = sf * exp(lnqf);
-            if (M::REV[j]) q -= sr * exp(lnqr);
-        }
-        if (M::TYPE[j] == RX_TB) q *= r.M;
-#pragma unroll
-        for (int i = 0; i < M::NRE[j]; i++) om[M::RSP[j][i]] -= M::RNU[j][i] * q;
-#pragma unroll
-        for (int i = 0; i < M::NPR[j]; i++) om[M::PSP[j][i]] += M::PNU[j][i] * q;
-        // keep the scheduler from interleaving reactions (live ranges of the
-        // inline exp/log sequences would otherwise overflow the register file)
+        constexpr int G = CHEM_RXN_GROUP;
+        double q[G];
+        q[0] = rxn_net<M, j>(P, E);
+        if constexpr (G > 1 && j + 1 < M::NR) q[1] = rxn_net<M, (j + 1 < M::NR ? j + 1 : j)>(P, E);
+        if constexpr (G > 2 && j + 2 < M::NR) q[2] = rxn_net<M, (j + 2 < M::NR ? j + 2 : j)>(P, E);
+        rxn_scatter<M, j>(q[0], om);
+        if constexpr (G > 1 && j + 1 < M::NR) rxn_scatter<M, (j + 1 < M::NR ? j + 1 : j)>(q[1], om);
+        if constexpr (G > 2 && j + 2 < M::NR) rxn_scatter<M, (j + 2 < M::NR ? j + 2 : j)>(q[2], om);
         __builtin_amdgcn_sched_barrier(0);
-        rhs_loop<M, j + 1>(P, E, om);
+        rhs_loop<M, j + G>(P, E, om);
     }
 }
 

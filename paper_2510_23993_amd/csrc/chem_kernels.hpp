@@ -175,6 +175,78 @@ __global__ void __launch_bounds__(256) k_scatter_unfinished(const uint8_t* __res
     if (a) ids[off[blockIdx.x] + r] = (int)s;
 }
 
+// ------------------------------------------- cost-ordered compaction
+// Per-cell completion prediction for the order in which lanes take cells:
+// the number of tolerance units the state moves per dt at the start,
+// s = dt max_i |f_i(y0)| / (rtol |y0_i| + atol) (one RHS per active cell),
+// ranks cells by the work the integrator will spend on them.  Cells are
+// taken longest first (bucket 0 = largest s, one bucket per factor 2 of s),
+// so long cells do not start last and leave a tail of idle lanes.  Results
+// do not depend on the order: each cell is integrated by itself.
+constexpr int COST_BUCKETS = 64;
+
+template <class M>
+__global__ void __launch_bounds__(256) k_cost_key(const Params<M>* __restrict__ Pp,
+                                                  const DevBox* __restrict__ boxes, int nbox,
+                                                  const int* __restrict__ ids, const int* __restrict__ n_items,
+                                                  double rtol, double atol, uint8_t* __restrict__ key,
+                                                  int* __restrict__ bcnt, int nb) {
+    __shared__ int hist[COST_BUCKETS];
+    const Params<M>& P = *Pp;
+    const int n = *n_items;
+    const int64_t slot = blockIdx.x * 256ll + threadIdx.x;
+    if (threadIdx.x < COST_BUCKETS) hist[threadIdx.x] = 0;
+    __syncthreads();
+    if (slot < n) {
+        const int64_t g = ids[slot];
+        const DevBox& B = boxes[find_box(boxes, nbox, g)];
+        const int64_t i = g - B.off;
+        double y[M::N], f[M::N];
+#pragma unroll
+        for (int k = 0; k < M::NS; k++) y[k] = B.Y[k * B.ldY + i];
+        y[M::NS] = B.T[i];
+        rhs(P, B.rho[i], y, f);
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < M::N; k++) s = fmax(s, fabs(f[k]) / (rtol * fabs(y[k]) + atol));
+        s *= B.dt;
+        // s that is not finite (a state the integrator will reject) goes first
+        const int lg = isfinite(s) ? (int)fmin(floor(log2(fmax(s, 1.0))), (double)(COST_BUCKETS - 1)) : COST_BUCKETS - 1;
+        const int b = COST_BUCKETS - 1 - lg;
+        key[slot] = (uint8_t)b;
+        atomicAdd(&hist[b], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < COST_BUCKETS) bcnt[threadIdx.x * nb + blockIdx.x] = hist[threadIdx.x];
+}
+
+// ids_out[off[b * nb + block] + rank] = ids_in[slot], rank = the slot's
+// position among the block's slots of bucket b (in slot order): a stable
+// counting sort by bucket.
+__global__ void __launch_bounds__(256) k_bucket_scatter(const uint8_t* __restrict__ key,
+                                                        const int* __restrict__ ids_in,
+                                                        const int* __restrict__ n_items,
+                                                        const int* __restrict__ off, int nb,
+                                                        int* __restrict__ ids_out) {
+    __shared__ int wc[4][COST_BUCKETS];
+    const int n = *n_items;
+    const int64_t slot = blockIdx.x * 256ll + threadIdx.x;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int b = slot < n ? (int)key[slot] : -1;
+    int within = 0;
+    for (int bb = 0; bb < COST_BUCKETS; bb++) {
+        const unsigned long long m = wave_ballot(b == bb);
+        if (b == bb) within = __popcll(m & ((1ull << lane) - 1ull));
+        if (lane == 0) wc[w][bb] = __popcll(m);
+    }
+    __syncthreads();
+    if (b >= 0) {
+        int before = 0;
+        for (int q = 0; q < w; q++) before += wc[q][b];
+        ids_out[off[b * nb + blockIdx.x] + before + within] = ids_in[slot];
+    }
+}
+
 // --------------------------------------------------------- state preparation
 template <class M>
 __global__ void k_prepare(const Params<M>* __restrict__ Pp, int64_t n, const double* __restrict__ T,

@@ -23,6 +23,7 @@ ATM = 101325.0
 DATA = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data")
 M9_PATH = os.path.join(DATA, "m9.mech")
 M53_PATH = os.path.join(DATA, "m53.mech")
+M9_TWO_RANGE_PATH = os.path.join(DATA, "m9_two_range.mech")   # distinct NASA-7 sets below / above 1000 K
 
 # molecular weights of the M9 species [g/mol] from the standard atomic masses
 _W9 = np.array([2.016, 31.998, 18.015, 1.008, 15.999, 17.007, 33.006, 34.014, 28.014])

@@ -162,6 +162,41 @@ def make_m9(seed: int = M9_SEED) -> Mechanism:
 # 53-species C/H/O/N mechanism
 
 
+M9_TWO_RANGE_SEED = 1009
+
+
+def two_range_thermo(coeffs, kappa: float, Tmid: float = 1000.0):
+    """A NASA-7 high-temperature set that differs from the low set by
+    cp/R += kappa (T - Tmid)^2 for T >= Tmid, with the enthalpy and entropy
+    constants chosen so that h and s are continuous at Tmid (cp is C1 there).
+    The added cp term integrates to kappa (T - Tmid)^3 / 3 in h/R and to
+    kappa (T^2/2 - 2 Tmid T + Tmid^2 ln T) + const in s/R."""
+    a = list(coeffs)
+    hi = list(a)
+    hi[0] += kappa * Tmid * Tmid
+    hi[1] += -2.0 * kappa * Tmid
+    hi[2] += kappa
+    hi[5] += -kappa * Tmid ** 3 / 3.0
+    hi[6] += -kappa * Tmid * Tmid * (math.log(Tmid) - 1.5)
+    return a, hi
+
+
+def make_m9_two_range(seed: int = M9_TWO_RANGE_SEED) -> Mechanism:
+    """The 9-species mechanism with distinct NASA-7 sets below and above
+    Tmid = 1000 K (same reactions, so the same compiled structure): each
+    species' high set adds a seeded kappa (T - Tmid)^2 to cp/R, |kappa| in
+    [3e-8, 1.2e-7] (a 0.1-0.5 change of cp/R at 3000 K), with h, s and cp
+    continuous at Tmid."""
+    m = make_m9()
+    rng = np.random.default_rng(seed)
+    for sp in m.species:
+        kappa = float(rng.uniform(3e-8, 1.2e-7) * rng.choice([-1.0, 1.0]))
+        lo, hi = two_range_thermo(sp.nasa_low, kappa, sp.T_range[1])
+        sp.nasa_low, sp.nasa_high = lo, hi
+    m.name = "m9_two_range"
+    return m
+
+
 def _formula_name(comp: Dict[str, int]) -> str:
     s = ""
     for e in ("C", "H", "O", "N"):

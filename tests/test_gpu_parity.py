@@ -147,7 +147,10 @@ def test_bulk_sparse_bitwise_equals_plain(chem, mech, m9, group):
     for opts in ({"algorithm": 0}, {"algorithm": 1, "nactive_star": 0, "kmax_bulk": 3},
                  {"algorithm": 1, "nactive_star": 500, "kmax_bulk": 5},
                  {"algorithm": 1, "nactive_star": 0, "kmax_bulk": 2, "round_decay": 0.5},
-                 {"algorithm": 1, "max_rounds": 0}):
+                 {"algorithm": 1, "max_rounds": 0},
+                 # lanes take the cells in predicted-cost order (longest first)
+                 {"algorithm": 1, "max_rounds": 0, "order": 1},
+                 {"algorithm": 1, "nactive_star": 0, "kmax_bulk": 3, "order": 1}):
         ctx = chem.Context(mech, t_react_min=0.0, group=group, **opts)
         Yg, Tg, st, stats = run_gpu(ctx, rho, e, c.Y, c.T, c.dt, RTOL_C1, ATOL_C1)
         assert np.all(st == 0)

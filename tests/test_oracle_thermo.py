@@ -83,3 +83,35 @@ def test_state_from_TPY_ideal_gas(m9):
     assert np.allclose(p, rho * R * T / Wmix, rtol=1e-14)
     for i in range(n):
         assert e[i] == pytest.approx(m9.e_mass(T[i], Y[:, i]), rel=1e-15)
+
+
+def test_two_range_thermo_continuous_at_tmid(oracle_lib):
+    # the two-range variant of the 9-species mechanism: distinct sets below and
+    # above 1000 K, cp, dcp/dT, h and s continuous at Tmid, the high set in use
+    # above it (cp differs from the low polynomial by kappa (T - Tmid)^2)
+    from synth import fields
+    from synth.mechgen import make_m9_two_range
+    o = oracle_lib.Oracle(fields.M9_TWO_RANGE_PATH)
+    m = make_m9_two_range()
+    for k in range(o.ns):
+        below = o.thermo(k, 1000.0 * (1 - 1e-12))
+        at = o.thermo(k, 1000.0)
+        assert np.allclose(below[:3], at[:3], rtol=1e-9), (k, below, at)
+        assert below[3] == pytest.approx(at[3], rel=1e-6, abs=1e-12)
+        lo = m.species[k].nasa_low
+        T = 2500.0
+        cp_lo = sum(lo[i] * T ** i for i in range(5))
+        kappa = m.species[k].nasa_high[2] - lo[2]
+        assert abs(kappa) > 1e-8
+        assert o.thermo(k, T)[0] == pytest.approx(cp_lo + kappa * (T - 1000.0) ** 2, rel=1e-12)
+        for T in (700.0, 1300.0, 2800.0):     # calculus identities on both sides
+            d = 1e-3 * T
+            dhdT = _richardson(lambda t: t * o.thermo(k, t)[1], T, d)
+            assert dhdT == pytest.approx(o.thermo(k, T)[0], rel=1e-9)
+
+
+def test_two_range_file_matches_generator():
+    from synth import fields
+    from synth.mechfile import format_mechanism
+    from synth.mechgen import make_m9_two_range
+    assert open(fields.M9_TWO_RANGE_PATH).read() == format_mechanism(make_m9_two_range())
