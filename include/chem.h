@@ -200,6 +200,26 @@ int chem_integrate(chem_ctx_t c, int64_t ncell, const double* rho, const double*
                    int64_t ldY, double* T, const uint8_t* skip_mask, uint8_t* status, double dt,
                    double rtol, double atol, chem_stats* stats);
 
+/* Allocation-free variant of chem_integrate, for callers that cannot
+ * allocate device memory: code under hipGraph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, layout and per-cell
+ * results as chem_integrate with the cooperative schedule and no bulk rounds
+ * (option group > 0, or 16 lanes per cell for up to 16 state components and
+ * 64 above; screen, compaction, integration to completion); the other
+ * options apply as there.  Its workspace is one file-scope device array of
+ * about 10.5 MB per GPU, held until the process ends, so
+ *   - ncell is at most 1048576 (CHEM_E_INVAL above);
+ *   - every call on a GPU uses that GPU's one array: calls that overlap on
+ *     one GPU (on different streams or from different threads) race and
+ *     give wrong results; calls in one stream are ordered and safe;
+ *   - it needs surrogate 0 and method 0 (CHEM_E_STATE otherwise).
+ * The call calls no hipMalloc / hipFree and returns without synchronising;
+ * it never fills statistics (check status[] for cells that did not finish).
+ * Errors as chem_integrate (negative codes only). */
+int chem_integrate_noalloc(chem_ctx_t c, int64_t ncell, const double* rho, const double* e, double* Y,
+                           int64_t ldY, double* T, const uint8_t* skip_mask, uint8_t* status, double dt,
+                           double rtol, double atol);
+
 /* Integrate many separately allocated boxes, each over its own dt, in one
  * enqueued pipeline (one screening pass, one compaction, persistent
  * integration kernels over all boxes; Sec. 3.2.1 multigrid fusion with an

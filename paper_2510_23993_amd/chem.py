@@ -56,7 +56,7 @@ EXPORTS = ["chem_load_mechanism", "chem_mech_info", "chem_species_name", "chem_f
            "chem_mlp_nparams", "chem_mlp_workspace_floats", "chem_mlp_forward", "chem_mlp_backward",
            "chem_mlp_mse", "chem_mlp_adam", "chem_mlp_gather", "chem_mlp_colstats", "chem_mlp_standardize",
            "chem_mlp_colrange", "chem_surrogate_pairs", "chem_mech_hash",
-           "chem_flow_step", "chem_strang_step"]
+           "chem_flow_step", "chem_strang_step", "chem_integrate_noalloc"]
 
 
 def lib():
@@ -86,6 +86,7 @@ def lib():
     L.chem_load_surrogate.argtypes = [vp, C.c_char_p]
     L.chem_integrate.argtypes = [vp, i64, vp, vp, vp, i64, vp, vp, vp, dbl, dbl, dbl,
                                  C.POINTER(chem_stats)]
+    L.chem_integrate_noalloc.argtypes = [vp, i64, vp, vp, vp, i64, vp, vp, vp, dbl, dbl, dbl]
     L.chem_integrate_boxes.argtypes = [vp, C.c_int, C.POINTER(chem_box), dbl, dbl, C.POINTER(chem_stats)]
     L.chem_flow_step.argtypes = [vp, i64, dbl, dbl, vp, i64, vp]
     L.chem_strang_step.argtypes = [vp, i64, dbl, dbl, vp, i64, vp, vp, dbl, dbl, C.POINTER(chem_stats)]
@@ -217,6 +218,18 @@ class Context:
         d = st.as_dict()
         d["rc"] = rc
         return d
+
+    def integrate_noalloc(self, rho, e, Y, T, dt, rtol, atol, mask=None, status=None):
+        """chem_integrate_noalloc: as integrate() without statistics, on the
+        library's fixed device scratch (no allocation; at most 2^20 cells)."""
+        n = rho.shape[0]
+        _check_f64("rho", rho, (n,))
+        _check_f64("e", e, (n,))
+        _check_f64("T", T, (n,))
+        _check_f64("Y", Y, (self.mech.ns, n))
+        return _check(lib().chem_integrate_noalloc(self._h, n, _ptr(rho), _ptr(e), _ptr(Y), n, _ptr(T),
+                                                   _ptr(mask), _ptr(status), float(dt), float(rtol),
+                                                   float(atol)))
 
     def flow_step(self, U, T, dx, dt):
         """One SSP-RK2 step of the 1-D flow: U [3+ns, n], T [n] (in: guess,

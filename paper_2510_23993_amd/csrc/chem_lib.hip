@@ -775,6 +775,62 @@ int pipeline_any(chem_ctx_s* c, int64_t total, int nbox, double rtol, double ato
     return pipeline_coop(c, G, total, nbox, rtol, atol);
 }
 
+// ------------------------------------------------ allocation-free entry point
+// chem_integrate_noalloc runs the cooperative schedule (G lanes per cell,
+// screen -> compaction -> persistent integration to completion, no bulk
+// rounds, so no save area) on a workspace carved from one file-scope device
+// array instead of context buffers.  Each device holds its own copy of the
+// array; its address is taken once per device with that device current.
+constexpr int64_t NOALLOC_MAX_CELLS = int64_t(1) << 20;
+constexpr size_t na_align(size_t b) { return (b + 255) / 256 * 256; }
+constexpr int64_t NA_NB = NOALLOC_MAX_CELLS / 256 + 1;
+constexpr size_t NA_BOX = 0;
+constexpr size_t NA_INTS = NA_BOX + na_align(sizeof(DevBox));
+constexpr size_t NA_CTR = NA_INTS + na_align(sizeof(int) * I_COUNT);
+constexpr size_t NA_BCNT = NA_CTR + na_align(2 * sizeof(Counters));
+constexpr size_t NA_BOFF = NA_BCNT + na_align(sizeof(int) * NA_NB);
+constexpr size_t NA_ST = NA_BOFF + na_align(sizeof(int) * NA_NB);
+constexpr size_t NA_FLAG = NA_ST + na_align(NOALLOC_MAX_CELLS);
+constexpr size_t NA_ACT = NA_FLAG + na_align(NOALLOC_MAX_CELLS);
+constexpr size_t NA_SP = NA_ACT + na_align(sizeof(int) * NOALLOC_MAX_CELLS);
+constexpr size_t NA_BYTES = NA_SP + na_align(sizeof(int) * NOALLOC_MAX_CELLS);   // about 10.5 MB
+
+std::once_flag g_na_once[MAX_DEVICES];
+char* g_na_ptr[MAX_DEVICES];
+hipError_t g_na_err[MAX_DEVICES];
+
+}  // namespace
+
+// The array itself.  In host code its name is only a stand-in for the
+// symbol: every host use goes through the device address g_na_ptr[device].
+static __device__ __align__(256) unsigned char scratch[NA_BYTES];
+
+namespace {
+
+// With `device` current: look up this device's copy of the array.
+int noalloc_init(int device) {
+    std::call_once(g_na_once[device], [&] {
+        void* ptr = nullptr;
+        g_na_err[device] = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (g_na_err[device] == hipSuccess) g_na_ptr[device] = (char*)ptr;
+    });
+    if (g_na_err[device] != hipSuccess)
+        return fail(CHEM_E_HIP, std::string("scratch address of the allocation-free entry point: ") +
+                                    hipGetErrorString(g_na_err[device]));
+    if (!g_na_ptr[device]) return fail(CHEM_E_HIP, "scratch address of the allocation-free entry point is null");
+    return 0;
+}
+
+__global__ void k_put_box(DevBox* dst, DevBox b) {
+    if (threadIdx.x == 0) *dst = b;
+}
+
+WsView noalloc_view(char* base) {
+    return WsView{(uint8_t*)(base + NA_ST), (int*)(base + NA_ACT), (int*)(base + NA_SP), (uint8_t*)(base + NA_FLAG),
+                  (int*)(base + NA_BCNT), (int*)(base + NA_BOFF), (int*)(base + NA_INTS),
+                  (Counters*)(base + NA_CTR), (const DevBox*)(base + NA_BOX), nullptr, NOALLOC_MAX_CELLS};
+}
+
 template <int G, int R>
 int eval_coop_t(chem_ctx_s* c, int64_t n, const double* rho, const double* y, double* f, double* J) {
     const int NC = G * R, ngrp = 64 / G;
@@ -1134,6 +1190,7 @@ int chem_ctx_create(chem_mech_t m, int device, void* stream, chem_ctx_t* out) {
     HIPCHK(hipGetDeviceProperties(&prop, device));
     c->ncu = prop.multiProcessorCount;
     if (int rc = coop_lds_init(device)) return rc;
+    if (int rc = noalloc_init(device)) return rc;
     for (auto& e : c->ev_copy) {
         HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         HIPCHK(hipEventRecord(e, c->stream));
@@ -1228,6 +1285,36 @@ int chem_integrate(chem_ctx_t c, int64_t ncell, const double* rho, const double*
     if (ncell < 0) return fail(CHEM_E_INVAL, "ncell < 0");
     chem_box b{ncell, rho, e, Y, ldY, T, mask, status, dt, 0};
     return run(c, {b}, rtol, atol, st, false);
+}
+
+int chem_integrate_noalloc(chem_ctx_t c, int64_t ncell, const double* rho, const double* e, double* Y,
+                           int64_t ldY, double* T, const uint8_t* mask, uint8_t* status, double dt, double rtol,
+                           double atol) {
+    if (!c) return fail(CHEM_E_INVAL, "NULL context");
+    if (ncell < 0) return fail(CHEM_E_INVAL, "ncell < 0");
+    if (ncell > NOALLOC_MAX_CELLS)
+        return fail(CHEM_E_INVAL, "chem_integrate_noalloc takes at most 1048576 cells per call");
+    if (!(rtol > 0) || !(atol >= 0) || !std::isfinite(rtol) || !std::isfinite(atol))
+        return fail(CHEM_E_INVAL, "rtol must be > 0 and atol >= 0");
+    const chem_box b{ncell, rho, e, Y, ldY, T, mask, status, dt, 0};
+    if (int rc = check_box(b, c->m->hm.ns)) return rc;
+    if (c->opt.surrogate || c->opt.method != 0)
+        return fail(CHEM_E_STATE, "chem_integrate_noalloc runs the implicit integrator only (surrogate 0, method 0)");
+    if (ncell == 0) return 0;
+    char* base = g_na_ptr[c->device];
+    if (!base) return fail(CHEM_E_STATE, "the allocation-free scratch of this device was not set up");
+    HIPCHK(hipSetDevice(c->device));
+    const int n = c->m->hm.ns + 1;
+    int G = c->opt.group > 0 ? c->opt.group : (n <= 16 ? 16 : 64);
+    if (G * coop_R(G) < n) G = 64;
+    const DevBox db{rho, e, Y, T, mask, status, ncell, ldY, 0, dt};
+    const WsView w = noalloc_view(base);
+    hipLaunchKernelGGL(k_put_box, dim3(1), dim3(64), 0, c->stream, (DevBox*)(base + NA_BOX), db); LAUNCHED();
+    const bool timing = c->timing;
+    c->timing = false;
+    const int rc = pipeline_coop_ws(c, G, ncell, 1, rtol, atol, w, 0);
+    c->timing = timing;
+    return rc;
 }
 
 int chem_integrate_boxes(chem_ctx_t c, int nbox, const chem_box* boxes, double rtol, double atol,

@@ -55,6 +55,7 @@ def test_null_arguments():
     assert L.chem_set_option(None, b"algorithm", 1.0) == -1
     assert L.chem_load_mechanism(None, None) == -1
     assert L.chem_integrate(None, 0, None, None, None, 0, None, None, None, 1.0, 1.0, 1.0, None) == -1
+    assert L.chem_integrate_noalloc(None, 0, None, None, None, 0, None, None, None, 1.0, 1.0, 1.0) == -1
     assert L.chem_synchronize(None) == -1
     assert b"NULL" in L.chem_last_error()
 
