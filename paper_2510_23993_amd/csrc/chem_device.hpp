@@ -33,6 +33,25 @@ __device__ __forceinline__ double mlog(double x) {
     else return log(x);
 }
 
+// The parameter block as seen by one evaluation.  The kernels run their
+// evaluations inside loops; without this the compiler hoists every
+// parameter load out of those loops and keeps hundreds of uniform values
+// live across them (spilled to vector registers and scratch).  Passing the
+// block's address through an empty asm makes it opaque, so each evaluation
+// reloads its parameters through the scalar cache where it uses them.
+template <class T>
+__device__ __forceinline__ const T& fresh(const T& p) {
+#if defined(__HIP_DEVICE_COMPILE__) && !defined(CHEM_NO_OPAQUE)
+    // read-only for the whole kernel (constant address space): loads through
+    // it go through the scalar cache
+    const __attribute__((address_space(4))) T* q = (const __attribute__((address_space(4))) T*)&p;
+    asm volatile("" : "+s"(q));
+    return *(const T*)q;
+#else
+    return p;
+#endif
+}
+
 // ---------------------------------------------------------------- thermo
 // NASA-7 with pre-divided coefficients (host packs them):
 //   h/RT = H0 + T(H1 + T(H2 + T(H3 + T H4))) + H5/T
@@ -314,7 +333,8 @@ __device__ __forceinline__ void rhs_loop(const Params<M>& P, const CellEval<M>& 
 
 // f = dy/dt for y = (Y_1..Y_NS, T) at constant rho and e.
 template <class M>
-__device__ __forceinline__ void rhs(const Params<M>& P, double rho, const double* y, double* f) {
+__device__ __forceinline__ void rhs(const Params<M>& Pin, double rho, const double* y, double* f) {
+    const Params<M>& P = fresh(Pin);
     CellEval<M> E;
     cell_eval(P, rho, y, E);
     double om[M::NS];
@@ -335,15 +355,19 @@ __device__ __forceinline__ void rhs(const Params<M>& P, double rho, const double
 }
 
 // ---------------------------------------------------------------- Jacobian
-// The species rows J[k][m] = (W_k/W_m) sum_j nu_kj dq_j/dC_m are accumulated
-// entry by entry through acc(k, m, v) (into the lane's LDS Newton matrix in
-// the integrator), so no dense d(omega)/dC block is held in registers.  The
-// temperature row needs dSm[m] = sum_k u_k d omega_k/dC_m, om and dwT, which
-// are kept as NS-vectors.
-template <class M, int j, class Acc>
-__device__ __forceinline__ void jac_loop(const Params<M>& P, const CellEval<M>& E, const double* invC,
-                                         double T, double* om, double* dwT, double* dSm,
-                                         Acc& acc) {
+// Analytic Jacobian of the reactor RHS, organised for registers: one pass
+// over the reactions keeps each reaction's forward and reverse rates of
+// progress (times [M] for third-body reactions) and the dense third-body /
+// falloff factor, together with the production rates and their temperature
+// derivatives; a second pass builds dω/dC one column at a time,
+//   G[k][m] = (1/C_m) Σ_j ν_kj (ν'_mj qf_j − ν''_mj qr_j) + Σ_j ν_kj α_jm g_j,
+// whose stoichiometric products are compile-time constants, and hands each
+// finished entry over scaled, J[k][m] = (W_k / W_m) G[k][m], through
+// store(i, j, v) (every entry of the n x n Jacobian exactly once, the
+// species block by columns, then the temperature column).
+template <class M, int j>
+__device__ __forceinline__ void jc_rates(const Params<M>& P, const CellEval<M>& E, double* QF, double* QR,
+                                         double* G, double* om, double* dwT) {
     if constexpr (j < M::NR) {
         constexpr int TY = M::TYPE[j];
         RxnK r;
@@ -353,8 +377,6 @@ __device__ __forceinline__ void jac_loop(const Params<M>& P, const CellEval<M>& 
         const double qf = sf * mexp<M>(lnqf);
         const double qr = M::REV[j] ? sr * mexp<M>(lnqr) : 0.0;
         const double mul = (TY == RX_TB) ? r.M : 1.0;
-        const double net = qf - qr;
-        // d ln qf/dT = dlnkf, d ln qr/dT = dlnkf - dlnKc
         double dlnKc = 0.0;
         if (M::REV[j]) {
             double sh = 0.0;
@@ -364,87 +386,133 @@ __device__ __forceinline__ void jac_loop(const Params<M>& P, const CellEval<M>& 
             for (int i = 0; i < M::NRE[j]; i++) sh -= M::RNU[j][i] * E.h_RT[M::RSP[j][i]];
             dlnKc = (sh - M::DNU[j]) * E.invT;
         }
-        const double dqdT = mul * (qf * r.dlnkf_dT - qr * (r.dlnkf_dT - dlnKc));
+        const double net = qf - qr;
         const double q = mul * net;
-        // dense part of dq/dC_m (alpha_m g) from the third-body concentration
-        double g = 0.0;
-        if (TY == RX_TB) g = net;
-        if (TY == RX_FO) g = net * r.dlnkf_dlnM / fmax(r.M, 1e-300);
-        // participant k with signed coefficient s (negative for reactants)
-        auto row = [&](int k, double s) {
-            om[k] += s * q;
-            dwT[k] += s * dqdT;
+        const double dqdT = mul * (qf * r.dlnkf_dT - qr * (r.dlnkf_dT - dlnKc));
+        QF[j] = mul * qf;
+        QR[j] = mul * qr;
+        G[j] = (TY == RX_TB) ? net : ((TY == RX_FO) ? net * r.dlnkf_dlnM / fmax(r.M, 1e-300) : 0.0);
 #pragma unroll
-            for (int i = 0; i < M::NRE[j]; i++) {
-                const int m = M::RSP[j][i];
-                const double v = s * mul * M::RNU[j][i] * qf * invC[m];
-                acc(k, m, P.W[k] * P.invW[m] * v);
-                dSm[m] += (E.h_RT[k] - 1.0) * T * v;
-            }
+        for (int i = 0; i < M::NRE[j]; i++) {
+            om[M::RSP[j][i]] -= M::RNU[j][i] * q;
+            dwT[M::RSP[j][i]] -= M::RNU[j][i] * dqdT;
+        }
 #pragma unroll
-            for (int i = 0; i < M::NPR[j]; i++) {
-                const int m = M::PSP[j][i];
-                const double v = -s * mul * M::PNU[j][i] * qr * invC[m];
-                acc(k, m, P.W[k] * P.invW[m] * v);
-                dSm[m] += (E.h_RT[k] - 1.0) * T * v;
-            }
-            if (TY != RX_ELEM) {
-#pragma unroll
-                for (int m = 0; m < M::NS; m++) {
-                    const double v = s * P.eff[j][m] * g;
-                    acc(k, m, P.W[k] * P.invW[m] * v);
-                    dSm[m] += (E.h_RT[k] - 1.0) * T * v;
-                }
-            }
-        };
-#pragma unroll
-        for (int i = 0; i < M::NRE[j]; i++) row(M::RSP[j][i], -(double)M::RNU[j][i]);
-#pragma unroll
-        for (int i = 0; i < M::NPR[j]; i++) row(M::PSP[j][i], (double)M::PNU[j][i]);
+        for (int i = 0; i < M::NPR[j]; i++) {
+            om[M::PSP[j][i]] += M::PNU[j][i] * q;
+            dwT[M::PSP[j][i]] += M::PNU[j][i] * dqdT;
+        }
         __builtin_amdgcn_sched_barrier(0);
-        jac_loop<M, j + 1>(P, E, invC, T, om, dwT, dSm, acc);
+        jc_rates<M, j + 1>(P, E, QF, QR, G, om, dwT);
     }
 }
 
-// Analytic Jacobian of the reactor RHS.  acc(i, j, v) adds v to entry (i, j)
-// of the species rows (called several times per entry); put(i, j, v) sets the
-// last column and the temperature row once per entry.
-template <class M, class Acc, class Put>
-__device__ __forceinline__ void jac_eval(const Params<M>& P, double rho, const double* y, Acc& acc,
-                                         Put put) {
-    constexpr int NS = M::NS;
+// signed stoichiometric coefficient of species k in reaction j (products
+// positive, reactants negative), summed over the participant lists
+template <class M>
+__device__ __forceinline__ constexpr int nu_of(int j, int k) {
+    int v = 0;
+    for (int i = 0; i < M::NPR[j]; i++)
+        if (M::PSP[j][i] == k) v += M::PNU[j][i];
+    for (int i = 0; i < M::NRE[j]; i++)
+        if (M::RSP[j][i] == k) v -= M::RNU[j][i];
+    return v;
+}
+
+template <class M>
+__device__ __forceinline__ constexpr int nuf_of(int j, int k) {   // reactant coefficient
+    int v = 0;
+    for (int i = 0; i < M::NRE[j]; i++)
+        if (M::RSP[j][i] == k) v += M::RNU[j][i];
+    return v;
+}
+
+template <class M>
+__device__ __forceinline__ constexpr int nur_of(int j, int k) {   // product coefficient
+    int v = 0;
+    for (int i = 0; i < M::NPR[j]; i++)
+        if (M::PSP[j][i] == k) v += M::PNU[j][i];
+    return v;
+}
+
+template <class M, class Store>
+__device__ __forceinline__ void jac_cols(const Params<M>& Pin, double rho, const double* y, Store store) {
+    const Params<M>& P = fresh(Pin);
+    constexpr int NS = M::NS, NR = M::NR;
     CellEval<M> E;
     cell_eval(P, rho, y, E);
     const double T = y[NS];
-    double invC[NS], uk[NS], om[NS], dwT[NS], dSm[NS];
+    double invC[NS], om[NS], dwT[NS], QF[NR], QR[NR], G[NR];
 #pragma unroll
     for (int k = 0; k < NS; k++) {
         const double aC = fmax(fabs(E.C[k]), C_FLOOR);
         invC[k] = (E.C[k] < 0.0) ? -1.0 / aC : 1.0 / aC;
-        om[k] = dwT[k] = dSm[k] = 0.0;
+        om[k] = dwT[k] = 0.0;
     }
-    jac_loop<M, 0>(P, E, invC, T, om, dwT, dSm, acc);
+    jc_rates<M, 0>(P, E, QF, QR, G, om, dwT);
+    double uk[NS];
 #pragma unroll
-    for (int k = 0; k < NS; k++) uk[k] = (E.h_RT[k] - 1.0) * T;  // u_k / R (molar)
+    for (int k = 0; k < NS; k++) uk[k] = (E.h_RT[k] - 1.0) * T;   // u_k / R (molar)
     const double irho = 1.0 / rho;
-    double cvs = 0.0, dcvs = 0.0, S = 0.0, cvk[NS];
+    double cvs = 0.0, dcvs = 0.0, S = 0.0;
 #pragma unroll
     for (int k = 0; k < NS; k++) {
-        cvk[k] = cp_R(P, k, T) - 1.0;   // c_v,k / R (molar)
-        cvs += y[k] * P.invW[k] * cvk[k];
+        const double cvk = cp_R(P, k, T) - 1.0;   // c_v,k / R (molar)
+        cvs += y[k] * P.invW[k] * cvk;
         dcvs += y[k] * P.invW[k] * dcp_R_dT(P, k, T);
         S += uk[k] * om[k];
     }
     const double fT = -S * irho / cvs;
+    const double icvs = 1.0 / cvs;
+    // species columns
 #pragma unroll
-    for (int k = 0; k < NS; k++) put(k, NS, P.W[k] * irho * dwT[k]);
-    // temperature row: dT/dt = -sum u_k om_k / (rho c_v), dC_m/dY_m = rho/W_m
+    for (int m = 0; m < NS; m++) {
+        double col[NS];
 #pragma unroll
-    for (int m = 0; m < NS; m++) put(NS, m, -P.invW[m] / cvs * (dSm[m] + fT * cvk[m]));
+        for (int k = 0; k < NS; k++) col[k] = 0.0;
+#pragma unroll
+        for (int j = 0; j < NR; j++) {
+            const int af = nuf_of<M>(j, m), ar = M::REV[j] ? nur_of<M>(j, m) : 0;
+            if (af != 0 || ar != 0) {
+                const double d = (af != 0 ? af * QF[j] : 0.0) - (ar != 0 ? ar * QR[j] : 0.0);
+#pragma unroll
+                for (int k = 0; k < NS; k++) {
+                    const int nk = nu_of<M>(j, k);
+                    if (nk != 0) col[k] += nk * d;
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NS; k++) col[k] *= invC[m];
+#pragma unroll
+        for (int j = 0; j < NR; j++) {
+            if (M::TYPE[j] != RX_ELEM) {
+                const double d = P.eff[j][m] * G[j];
+#pragma unroll
+                for (int k = 0; k < NS; k++) {
+                    const int nk = nu_of<M>(j, k);
+                    if (nk != 0) col[k] += nk * d;
+                }
+            }
+        }
+        double dS = 0.0;
+#pragma unroll
+        for (int k = 0; k < NS; k++) {
+            dS += uk[k] * col[k];
+            store(k, m, (P.W[k] * P.invW[m]) * col[k]);
+        }
+        const double cvm = cp_R(P, m, T) - 1.0;
+        store(NS, m, -P.invW[m] * icvs * (dS + fT * cvm));
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    // temperature column
     double dS = 0.0;
 #pragma unroll
-    for (int k = 0; k < NS; k++) dS += cvk[k] * om[k] + uk[k] * dwT[k];
-    put(NS, NS, -dS * irho / cvs - fT * dcvs / cvs);
+    for (int k = 0; k < NS; k++) {
+        dS += (cp_R(P, k, T) - 1.0) * om[k] + uk[k] * dwT[k];
+        store(k, NS, P.W[k] * irho * dwT[k]);
+    }
+    store(NS, NS, -dS * irho * icvs - fT * dcvs * icvs);
 }
 
 // Lanes of a 64-lane workgroup that carry a cell.  Each carries its NN x NN
@@ -465,15 +533,7 @@ template <class M>
 __device__ __forceinline__ void newton_matrix(const Params<M>& P, double rho, const double* y,
                                               double c, double* A) {
     constexpr int NN = M::NN, LW = lanes_per_wave<M>();
-#pragma unroll
-    for (int r = 0; r < NN - 1; r++)
-#pragma unroll
-        for (int q = 0; q < NN - 1; q++) A[(r * NN + q) * LW] = (r == q) ? 1.0 : 0.0;
-    auto acc = [&](int i, int j, double v) {
-        const int si = M::SYS[i], sj = M::SYS[j];
-        if (si >= 0 && sj >= 0) A[(si * NN + sj) * LW] -= c * v;
-    };
-    jac_eval<M>(P, rho, y, acc, [&](int i, int j, double v) {
+    jac_cols<M>(P, rho, y, [&](int i, int j, double v) {
         const int si = M::SYS[i], sj = M::SYS[j];
         if (si >= 0 && sj >= 0) A[(si * NN + sj) * LW] = (si == sj ? 1.0 : 0.0) - c * v;
     });

@@ -1,6 +1,6 @@
 // Kernels of the chemistry hot path (gfx950, wave64).  One reactor cell per
 // lane; the per-lane Newton matrix / LU lives in LDS, the BDF backward
-// differences in a per-lane global workspace slot (coalesced: lane-major).
+// differences in the lane's registers.
 //
 // Pipeline of the bulk-sparse algorithm (Alg. 3):
 //   k_screen    T from (e, Y), skip cold / masked cells, per-block counts
@@ -280,14 +280,7 @@ __global__ void k_eval_rhs(const Params<M>* __restrict__ Pp, int64_t n, const do
     rhs(P, rho[c], yy, ff);
 #pragma unroll
     for (int i = 0; i < M::N; i++) f[i * n + c] = ff[i];
-    if (J) {
-#pragma unroll
-        for (int i = 0; i < M::NS; i++)
-#pragma unroll
-            for (int j = 0; j < M::NS; j++) J[(i * M::N + j) * n + c] = 0.0;
-        auto acc = [&](int i, int j, double v) { J[(i * M::N + j) * n + c] += v; };
-        jac_eval<M>(P, rho[c], yy, acc, [&](int i, int j, double v) { J[(i * M::N + j) * n + c] = v; });
-    }
+    if (J) jac_cols<M>(P, rho[c], yy, [&](int i, int j, double v) { J[(i * M::N + j) * n + c] = v; });
 }
 
 // ------------------------------------------------------------ BDF stepper
@@ -299,8 +292,10 @@ __global__ void k_eval_rhs(const Params<M>* __restrict__ Pp, int64_t n, const do
 // Jacobian from an earlier step), local error d/(k+1), WRMS norm with
 // weights 1/(rtol |y| + atol).  The Newton convergence test, the update of
 // the differences on acceptance and the order selection follow SciPy's BDF
-// implementation (scipy/integrate/_ivp/bdf.py, BSD-3-Clause).  D lives in
-// global memory: D(j, i) at D[(j*N + i) * ld].
+// implementation (scipy/integrate/_ivp/bdf.py, BSD-3-Clause).  The
+// differences D[j][i] (j = 0..MAXORD+2) live in the lane's registers: every
+// access below uses indices that are compile-time constants once the loops
+// are unrolled (the order k only selects among them).
 
 __device__ __forceinline__ double gamma_k(int k) {  // sum_{i<=k} 1/i
     double g = 0.0;
@@ -336,8 +331,22 @@ __device__ __forceinline__ double wrms(const double* v, const double* isc) {
 
 // D_j <- nabla'^j P(t_n) on the grid of spacing rho*h (j = 1..k; D_0 unchanged):
 // T_ji = sum_m (-1)^m C(j,m) b_i(m rho), b_i(x) = prod_{l=1..i} (l - 1 - x)/l.
+// b_i(m rho) does not depend on j: one table of them, then the alternating
+// binomial sums with compile-time coefficients.
 template <int N>
-__device__ __forceinline__ void rescale(double* D, int64_t ld, int k, double r) {
+__device__ __forceinline__ void rescale(double (&D)[ND][N], int k, double r) {
+    double B[MAXORD + 1][MAXORD + 1];   // B[m][i] = b_i(m r)
+#pragma unroll
+    for (int m = 0; m <= MAXORD; m++) {
+        const double x = m * r;
+        double b = 1.0;
+        B[m][0] = 1.0;
+#pragma unroll
+        for (int l = 1; l <= MAXORD; l++) {
+            b *= (l - 1 - x) * (1.0 / l);
+            B[m][l] = b;
+        }
+    }
     double Tm[MAXORD + 1][MAXORD + 1];
 #pragma unroll
     for (int j = 1; j <= MAXORD; j++) {
@@ -346,11 +355,7 @@ __device__ __forceinline__ void rescale(double* D, int64_t ld, int k, double r) 
             double s = 0.0, binom = 1.0;
 #pragma unroll
             for (int m = 0; m <= j; m++) {
-                double b = 1.0;
-                const double x = m * r;
-#pragma unroll
-                for (int l = 1; l <= i; l++) b *= (l - 1 - x) * (1.0 / l);
-                s += ((m & 1) ? -binom : binom) * b;
+                s += ((m & 1) ? -binom : binom) * B[m][i];
                 binom = binom * (j - m) / (m + 1);
             }
             Tm[j][i] = s;
@@ -360,14 +365,14 @@ __device__ __forceinline__ void rescale(double* D, int64_t ld, int k, double r) 
     for (int c = 0; c < N; c++) {
         double d[MAXORD + 1];
 #pragma unroll
-        for (int i = 0; i <= MAXORD; i++) d[i] = (i <= k) ? D[(i * N + c) * ld] : 0.0;
+        for (int i = 0; i <= MAXORD; i++) d[i] = (i <= k) ? D[i][c] : 0.0;
 #pragma unroll
         for (int j = 1; j <= MAXORD; j++) {
             if (j <= k) {
                 double s = 0.0;
 #pragma unroll
                 for (int i = 0; i <= MAXORD; i++) s += Tm[j][i] * d[i];
-                D[(j * N + c) * ld] = s;
+                D[j][c] = s;
             }
         }
     }
@@ -399,7 +404,7 @@ __device__ __forceinline__ bool next_step(Lane<M>& L, double& fac, double& hn) {
 // re-samples the same interpolating polynomial.  The last step is flagged
 // there, so the next attempt lands exactly on t_end.
 template <class M>
-__device__ __forceinline__ int bdf_attempt(const Params<M>& P, Lane<M>& L, double* D, int64_t ld, double* A,
+__device__ __forceinline__ int bdf_attempt(const Params<M>& P, Lane<M>& L, double (&D)[ND][M::N], double* A,
                            double rtol, double atol) {
     constexpr int N = M::N;
     constexpr double EPS = 2.220446049250313e-16;
@@ -425,7 +430,7 @@ __device__ __forceinline__ int bdf_attempt(const Params<M>& P, Lane<M>& L, doubl
             double a = 0.0;
 #pragma unroll
             for (int j = 0; j <= MAXORD; j++)
-                if (j <= k) a += D[(j * N + i) * ld];
+                if (j <= k) a += D[j][i];
             yj[i] = a;
         }
         newton_matrix<M>(P, L.rho, yj, c, A);
@@ -447,7 +452,7 @@ __device__ __forceinline__ int bdf_attempt(const Params<M>& P, Lane<M>& L, doubl
 #pragma unroll
         for (int j = 0; j <= MAXORD; j++) {
             if (j <= k) {
-                const double dj = D[(j * N + i) * ld];
+                const double dj = D[j][i];
                 a += dj;
                 if (j >= 1) {
                     gj += 1.0 / j;
@@ -536,17 +541,18 @@ __device__ __forceinline__ int bdf_attempt(const Params<M>& P, Lane<M>& L, doubl
             L.jac_fresh = false;
 #pragma unroll
             for (int i = 0; i < N; i++) {
-                double dv[MAXORD + 3];
+                double dk1 = 0.0;   // D_{k+1}
 #pragma unroll
-                for (int j = 0; j <= MAXORD + 1; j++) dv[j] = (j <= k + 1) ? D[(j * N + i) * ld] : 0.0;
-                D[((k + 2) * N + i) * ld] = d[i] - D[((k + 1) * N + i) * ld];
+                for (int j = 1; j <= MAXORD + 1; j++)
+                    if (j == k + 1) dk1 = D[j][i];
                 double acc = d[i];
-                D[((k + 1) * N + i) * ld] = acc;
 #pragma unroll
-                for (int j = MAXORD; j >= 0; j--) {
-                    if (j <= k) {
-                        acc = dv[j] + acc;
-                        D[(j * N + i) * ld] = acc;
+                for (int j = ND - 1; j >= 0; j--) {
+                    if (j == k + 2) D[j][i] = d[i] - dk1;
+                    else if (j == k + 1) D[j][i] = d[i];
+                    else if (j <= k) {
+                        acc = D[j][i] + acc;
+                        D[j][i] = acc;
                     }
                 }
             }
@@ -559,12 +565,24 @@ __device__ __forceinline__ int bdf_attempt(const Params<M>& P, Lane<M>& L, doubl
                     double v[N];
                     if (k > 1) {
 #pragma unroll
-                        for (int i = 0; i < N; i++) v[i] = D[(k * N + i) * ld] * (1.0 / k);
+                        for (int i = 0; i < N; i++) {
+                            double a = 0.0;
+#pragma unroll
+                            for (int j = 2; j <= MAXORD; j++)
+                                if (j == k) a = D[j][i];
+                            v[i] = a * (1.0 / k);
+                        }
                         em = wrms<N>(v, ise);
                     }
                     if (k < MAXORD) {
 #pragma unroll
-                        for (int i = 0; i < N; i++) v[i] = D[((k + 2) * N + i) * ld] * (1.0 / (k + 2));
+                        for (int i = 0; i < N; i++) {
+                            double a = 0.0;
+#pragma unroll
+                            for (int j = 3; j <= MAXORD + 1; j++)
+                                if (j == k + 2) a = D[j][i];
+                            v[i] = a * (1.0 / (k + 2));
+                        }
                         ep = wrms<N>(v, ise);
                     }
                 }
@@ -592,7 +610,7 @@ __device__ __forceinline__ int bdf_attempt(const Params<M>& P, Lane<M>& L, doubl
     if (!next_step(L, fac, hn)) return SR_FAIL;
     resc = resc || L.last;
     if (resc) {
-        rescale<N>(D, ld, L.k, fac);
+        rescale<N>(D, L.k, fac);
         L.h = hn;
         L.neq = 0;
     }
@@ -602,7 +620,7 @@ __device__ __forceinline__ int bdf_attempt(const Params<M>& P, Lane<M>& L, doubl
 // Initial state of a fresh cell: D_0 = y0, D_1 = h f(y0), order 1, with the
 // starting step of Hairer, Norsett & Wanner (Solving ODEs I, Sec. II.4).
 template <class M>
-__device__ __forceinline__ void bdf_init(const Params<M>& P, Lane<M>& L, double* D, int64_t ld, const double* y0,
+__device__ __forceinline__ void bdf_init(const Params<M>& P, Lane<M>& L, double (&D)[ND][M::N], const double* y0,
                          double rtol, double atol) {
     constexpr int N = M::N;
     double f0[N], isc[N], y1[N], f1[N];
@@ -636,8 +654,10 @@ __device__ __forceinline__ void bdf_init(const Params<M>& P, Lane<M>& L, double*
     L.h = fmin(fmin(100.0 * h0, h1), L.tend);
 #pragma unroll
     for (int i = 0; i < N; i++) {
-        D[i * ld] = y0[i];
-        D[(N + i) * ld] = L.h * f0[i];
+        D[0][i] = y0[i];
+        D[1][i] = L.h * f0[i];
+#pragma unroll
+        for (int j = 2; j < ND; j++) D[j][i] = 0.0;
     }
     L.t = 0.0;
     L.k = 1;
@@ -676,8 +696,6 @@ struct IntArgs {
     int nstar;
     uint8_t* flag;            // per slot: 0 fresh, 1 saved, 2 done
     SaveArea sv;
-    double* laneD;            // ND * N rows x ldL
-    int64_t ldL;
     int kmax;
     double rtol, atol;
     Counters* ctr;
@@ -699,9 +717,7 @@ __global__ void __launch_bounds__(64) k_integrate(const Params<M>* __restrict__ 
         if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(a.rounds, 1);
     }
     const int64_t n_items = (MODE == PLAIN) ? a.n_items_host : (int64_t)*a.n_items_dev;
-    const int64_t lslot = blockIdx.x * 64ll + lane;
-    double* D = a.laneD + lslot;
-    const int64_t ld = a.ldL;
+    double D[ND][N];
 
     Lane<M> L;
     L.n_steps = L.n_att = L.n_rhs = L.n_jac = L.n_lu = L.n_solve = 0;
@@ -758,10 +774,8 @@ __global__ void __launch_bounds__(64) k_integrate(const Params<M>* __restrict__ 
             L.round_att = 0;
             if (MODE != PLAIN && a.flag[slot] == 1) {
                 const SaveArea& S = a.sv;
-                // copies are only partly unrolled: a full unroll keeps every
-                // element in flight at once and spills the integrator state
-#pragma unroll 4
-                for (int r = 0; r < ND * N; r++) D[r * ld] = S.D[r * S.ld + slot];
+#pragma unroll
+                for (int r = 0; r < ND * N; r++) D[r / N][r % N] = S.D[r * S.ld + slot];
 #pragma unroll 4
                 for (int r = 0; r < NN * NN; r++) A[r * LW] = S.LU[r * S.ld + slot];
 #pragma unroll
@@ -781,11 +795,11 @@ __global__ void __launch_bounds__(64) k_integrate(const Params<M>* __restrict__ 
 #pragma unroll
                 for (int k = 0; k < NS; k++) y0[k] = B.Y[k * B.ldY + i];
                 y0[NS] = B.T[i];
-                bdf_init(P, L, D, ld, y0, a.rtol, a.atol);
+                bdf_init(P, L, D, y0, a.rtol, a.atol);
             }
         }
         // ---- one step attempt
-        const int r = bdf_attempt(P, L, D, ld, A, a.rtol, a.atol);
+        const int r = bdf_attempt(P, L, D, A, a.rtol, a.atol);
         bool finished = false, save = false;
         uint8_t st = ST_DONE;
         if (r == SR_DONE) {
@@ -806,8 +820,8 @@ __global__ void __launch_bounds__(64) k_integrate(const Params<M>* __restrict__ 
                 const DevBox& B = a.boxes[bidx];
                 const int64_t i = g - B.off;
 #pragma unroll
-                for (int k = 0; k < NS; k++) B.Y[k * B.ldY + i] = D[k * ld];
-                B.T[i] = D[NS * ld];
+                for (int k = 0; k < NS; k++) B.Y[k * B.ldY + i] = D[0][k];
+                B.T[i] = D[0][NS];
                 // a cell the surrogate handed over reports that it was integrated instead
                 const uint8_t fin = (st == ST_DONE && a.st_int[g] == ST_SURR_REJ) ? (uint8_t)ST_SURR_REJ : st;
                 a.st_int[g] = fin;
@@ -816,8 +830,8 @@ __global__ void __launch_bounds__(64) k_integrate(const Params<M>* __restrict__ 
                 if (st != ST_DONE) incomplete++;
             } else {
                 const SaveArea& S = a.sv;
-#pragma unroll 4
-                for (int rr = 0; rr < ND * N; rr++) S.D[rr * S.ld + slot] = D[rr * ld];
+#pragma unroll
+                for (int rr = 0; rr < ND * N; rr++) S.D[rr * S.ld + slot] = D[rr / N][rr % N];
 #pragma unroll 4
                 for (int rr = 0; rr < NN * NN; rr++) S.LU[rr * S.ld + slot] = A[rr * LW];
 #pragma unroll

@@ -134,12 +134,12 @@ struct chem_ctx_s {
     Options opt;
     int ncu = 0;
     // workspace
-    Buf st_int, active, sparse, flag, bcnt, boff, ints, ctr, save, laneD, boxes;
+    Buf st_int, active, sparse, flag, bcnt, boff, ints, ctr, save, boxes;
     Buf key, bcnt64, boff64;   // cost-ordered compaction: bucket per slot, bucket-major block counts
     // flow step: primitives, face fluxes, the Runge-Kutta stage, chemistry inputs, failure count
     Buf fQ, fF, fU1, fchem, fbad;
     hipEvent_t evf[4] = {};
-    int64_t cap_cells = 0, cap_lanes = 0;
+    int64_t cap_cells = 0;
     // pinned staging ring of the box table: a call only waits for the upload
     // issued NSTAGE calls earlier, so back-to-back calls keep the host ahead
     static constexpr int NSTAGE = 8;
@@ -183,13 +183,13 @@ int lds_blocks_per_cu(int device) {
     return nb;
 }
 
-// Workspace for one call.  The save area and the lane area are laid out with
-// stride = this call's cell / lane count, so their sizes are checked against
-// exactly that; any reallocation invalidates a captured graph (its nodes hold
-// the old addresses).
-int ensure_ws(chem_ctx_s* c, int64_t cells, int64_t lanes, size_t per_slot, size_t lane_bytes) {
+// Workspace for one call.  The save area is laid out with stride = this
+// call's cell count, so its size is checked against exactly that; any
+// reallocation invalidates a captured graph (its nodes hold the old
+// addresses).
+int ensure_ws(chem_ctx_s* c, int64_t cells, size_t per_slot) {
     const int64_t nb = (cells + 255) / 256 + 1;
-    void* before[8] = {c->st_int.p, c->active.p, c->save.p, c->laneD.p, c->bcnt.p, c->key.p, c->bcnt64.p, c->boff64.p};
+    void* before[8] = {c->st_int.p, c->active.p, c->save.p, c->sparse.p, c->bcnt.p, c->key.p, c->bcnt64.p, c->boff64.p};
     if (c->st_int.grow(cells) || c->active.grow(cells * 4) || c->sparse.grow(cells * 4) ||
         c->flag.grow(cells) || c->bcnt.grow(nb * 4) || c->boff.grow(nb * 4) ||
         c->ints.grow(I_COUNT * 4) || c->ctr.grow(2 * sizeof(Counters)) || c->key.grow(cells) ||
@@ -197,10 +197,7 @@ int ensure_ws(chem_ctx_s* c, int64_t cells, int64_t lanes, size_t per_slot, size
         return fail(CHEM_E_NOMEM, "workspace allocation failed");
     if (c->save.grow(per_slot * (size_t)cells)) return fail(CHEM_E_NOMEM, "save-area allocation failed");
     c->cap_cells = cells;
-    if (c->laneD.grow(std::max<size_t>(8, lane_bytes * (size_t)lanes)))
-        return fail(CHEM_E_NOMEM, "lane workspace allocation failed");
-    c->cap_lanes = lanes;
-    void* after[8] = {c->st_int.p, c->active.p, c->save.p, c->laneD.p, c->bcnt.p, c->key.p, c->bcnt64.p, c->boff64.p};
+    void* after[8] = {c->st_int.p, c->active.p, c->save.p, c->sparse.p, c->bcnt.p, c->key.p, c->bcnt64.p, c->boff64.p};
     if (memcmp(before, after, sizeof before) && c->gexec) {
         (void)hipGraphExecDestroy(c->gexec);
         c->gexec = nullptr;
@@ -233,12 +230,6 @@ int64_t persistent_grid(chem_ctx_s* c) {
     return (int64_t)per_cu * c->ncu;
 }
 
-int64_t lanes_needed(chem_ctx_s* c, int64_t total) {
-    // the plain path launches one workgroup per lanes_per_wave cells
-    const int lw = c->m->ops ? c->m->ops->lanes_per_wave : 64;
-    return std::max<int64_t>(persistent_grid(c) * 64, c->opt.algorithm == 0 ? ((total + lw - 1) / lw) * 64 : 0);
-}
-
 // phase boundary event (eager calls that return statistics only)
 void mark(chem_ctx_s* c, int i) {
     if (c->timing) (void)hipEventRecord(c->evp[i], c->stream);
@@ -251,8 +242,7 @@ int pipeline_k(chem_ctx_s* c, int64_t total, int nbox, double rtol, double atol)
     const Options& o = c->opt;
     hipStream_t s = c->stream;
     const int64_t grid = persistent_grid(c);
-    int rc = ensure_ws(c, std::max<int64_t>(total, 1), lanes_needed(c, total), onelane_slot_bytes(N),
-                       sizeof(double) * ND * N);
+    int rc = ensure_ws(c, std::max<int64_t>(total, 1), onelane_slot_bytes(N));
     if (rc) return rc;
     const Params<M>* P = (const Params<M>*)c->m->dparams;
     const Params<K>* PK = (const Params<K>*)c->m->dparams;   // same layout
@@ -273,8 +263,6 @@ int pipeline_k(chem_ctx_s* c, int64_t total, int nbox, double rtol, double atol)
     a.active_ids = c->active.as<int>();
     a.flag = c->flag.as<uint8_t>();
     a.sv = save_area(c, N);
-    a.laneD = c->laneD.as<double>();
-    a.ldL = c->cap_lanes;
     a.rtol = rtol;
     a.atol = atol;
     a.ctr = ctr;
@@ -637,11 +625,11 @@ int prepare_ws(chem_ctx_s* c, int64_t total) {
     const int64_t cells = std::max<int64_t>(total, 1);
     if (G == 0) {
         const int N = c->m->hm.ns + 1;
-        return ensure_ws(c, cells, lanes_needed(c, total), onelane_slot_bytes(N), sizeof(double) * ND * N);
+        return ensure_ws(c, cells, onelane_slot_bytes(N));
     }
     const int NC = G * coop_R(G);
     const bool save = c->opt.algorithm == 1 && c->opt.max_rounds > 0;
-    return ensure_ws(c, cells, 1, save ? coop_slot_bytes(NC) : 8, 8);
+    return ensure_ws(c, cells, save ? coop_slot_bytes(NC) : 8);
 }
 
 // Device workspace of one cooperative pipeline run, as raw pointers (into the

@@ -81,7 +81,7 @@ int hs_integrate(const char* mech_path, int pow_mode, int64_t n, const double* r
     g_pow_mode = pow_mode;
     constexpr int N = M::N, NN = M::NN, LW = lanes_per_wave<M>();
     static double A[NN * NN * LW];
-    double D[ND * N];
+    double D[ND][N];
     for (int64_t i = 0; i < n; i++) {
         Lane<M> L{};
         L.rho = rho[i];
@@ -90,10 +90,10 @@ int hs_integrate(const char* mech_path, int pow_mode, int64_t n, const double* r
         double y0[N];
         for (int k = 0; k < M::NS; k++) y0[k] = Y[k * n + i];
         y0[M::NS] = T[i];
-        bdf_init(*P, L, D, 1, y0, rtol, atol);
+        bdf_init(*P, L, D, y0, rtol, atol);
         uint8_t st = ST_KMAX;
         for (;;) {
-            const int r = bdf_attempt(*P, L, D, 1, A, rtol, atol);
+            const int r = bdf_attempt(*P, L, D, A, rtol, atol);
             if (r == SR_DONE) {
                 st = ST_DONE;
                 break;
@@ -104,8 +104,8 @@ int hs_integrate(const char* mech_path, int pow_mode, int64_t n, const double* r
             }
             if (L.att >= kmax) break;
         }
-        for (int k = 0; k < M::NS; k++) Y[k * n + i] = D[k];
-        T[i] = D[M::NS];
+        for (int k = 0; k < M::NS; k++) Y[k * n + i] = D[0][k];
+        T[i] = D[0][M::NS];
         status[i] = st;
         attempts[i] = L.att;
     }
