@@ -312,7 +312,7 @@ def main():
         t0 = time.perf_counter()
         opts, best_ms = ctx.autotune([dict(rho=F.rho, e=F.e, Y=F.Y, T=F.T, status=F.status, dt=F.dt)], rtol, ATOL)
         tune = {"options": opts, "best_call_ms": best_ms, "seconds": time.perf_counter() - t0}
-    tuned_opts = {k: ctx.get_option(k) for k in ("group", "max_rounds", "nactive_star", "kmax_bulk", "grid_waves")}
+    tuned_opts = {k: ctx.get_option(k) for k in ("group", "max_rounds", "nactive_star", "kmax_bulk", "grid_waves", "order")}
     _, tuned_rows = sweep(torch, ctx, F, idx, Yr, Tr, rtols=(rtol,))
 
     # K pristine copies resident in HBM before the timed region
@@ -326,6 +326,8 @@ def main():
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
     stats = []
     torch.cuda.synchronize()
+    torch.cuda._sleep(1)   # marks the start of the timed calls in a kernel trace
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(K):
         evs[i][0].record(stream)
@@ -334,6 +336,7 @@ def main():
         evs[i][1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    torch.cuda._sleep(1)   # marks the end of the timed calls in a kernel trace
     ev_ms = [a.elapsed_time(b) for a, b in evs]
     value = n * K / wall
     del Ys, Ts
@@ -447,8 +450,9 @@ def bench_amr(args, torch, chem, fields, oracle, rtol, quiet=False):
     against one hipGraph-replayed pipeline over all boxes (default options and
     after chem_autotune), then the subcycled coarse step (level 0 once, level 1
     twice, level 2 four times).  Median of 3 steps each, the restore of the
-    initial state outside the HIP-event interval; a sample of active cells
-    against the oracle."""
+    initial state outside the HIP-event interval.  At fixed error: starting
+    from `rtol`, the loosest rtol of the sweep at which a sample of active
+    cells (one per even box) meets the budget against the oracle."""
     boxes = fields.c3_boxes()
     mech = chem.Mechanism(fields.M9_PATH)
     orc = oracle.Oracle(fields.M9_PATH)
@@ -469,11 +473,34 @@ def bench_amr(args, torch, chem, fields, oracle, rtol, quiet=False):
                     sample.append((i, j, c.T[j], c.p[j], c.Y[:, j].copy(), c.dt))
             ntot += F.n
     torch.cuda.synchronize()
+    refs = [oracle_reference(orc, np.array([T]), np.array([p]), Y.reshape(-1, 1), dt)[:2]
+            for (i, j, T, p, Y, dt) in sample]
 
     def reset():
         for d in dev_boxes:
             d["Y"].copy_(d["Y0"])
             d["T"].copy_(d["T0"])
+
+    def sample_errors():
+        errs = []
+        for (i, j, T, p, Y, dt), (Yr, Tr) in zip(sample, refs):
+            Yg = dev_boxes[i]["Y"][:, j].cpu().numpy().reshape(-1, 1)
+            Tg = dev_boxes[i]["T"][j].cpu().numpy().reshape(1)
+            errs.append(rel_errors(Yg, Tg, Yr, Tr))
+        return max(e[0] for e in errs), max(e[1] for e in errs)
+
+    sweep_rows = []
+    with torch.cuda.stream(stream):
+        probe = chem.Context(mech, stream=stream, use_graph=0)
+        for r in [x for x in RTOLS if x <= rtol]:
+            reset()
+            st = probe.integrate_boxes(dev_boxes, r, ATOL)
+            rel, dT = sample_errors()
+            ok = rel <= BUDGET_REL and dT <= BUDGET_T and st["n_incomplete"] == 0
+            sweep_rows.append({"rtol": r, "max_rel": rel, "max_dT_K": dT, "meets_budget": ok})
+            if ok:
+                rtol = r
+                break
 
     def timed(fn, reps=3):
         with torch.cuda.stream(stream):
@@ -521,14 +548,7 @@ def bench_amr(args, torch, chem, fields, oracle, rtol, quiet=False):
         reset()
         st = tuned.integrate_boxes(dev_boxes, rtol, ATOL)
     torch.cuda.synchronize()
-    errs = []
-    for (i, j, T, p, Y, dt) in sample:
-        Yr, Tr, _ = oracle_reference(orc, np.array([T]), np.array([p]), Y.reshape(-1, 1), dt)
-        Yg = dev_boxes[i]["Y"][:, j].cpu().numpy().reshape(-1, 1)
-        Tg = dev_boxes[i]["T"][j].cpu().numpy().reshape(1)
-        errs.append(rel_errors(Yg, Tg, Yr, Tr))
-    rel = max(e[0] for e in errs)
-    dT = max(e[1] for e in errs)
+    rel, dT = sample_errors()
     ms = res["graph_autotuned"]
     out = {"workload": f"AMR batching: 400 boxes over 3 levels ({ntot} cells), jet-in-crossflow-like field, "
                        "dt 4e-8/2e-8/1e-8 s by level, 9-species mechanism",
@@ -541,6 +561,7 @@ def bench_amr(args, torch, chem, fields, oracle, rtol, quiet=False):
                          "cell_steps_per_s": sub_cells / (res["subcycled_graph_autotuned"] * 1e-3)},
            "oracle_sample": {"cells": len(sample), "max_rel": rel, "max_dT_K": dT,
                              "meets_budget": rel <= BUDGET_REL and dT <= BUDGET_T},
+           "fixed_error_sweep": sweep_rows,
            "stats": {k: st[k] for k in ("n_active0", "n_active_after_bulk", "n_bulk_rounds", "steps_total",
                                         "t_total_ms", "t_screen_ms", "t_bulk_ms", "t_sparse_ms")}}
     if quiet:

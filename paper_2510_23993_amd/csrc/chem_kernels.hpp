@@ -98,6 +98,46 @@ __global__ void __launch_bounds__(1024) k_scan(const int* __restrict__ cnt, int 
     if (t == 1023) *total = part[1023];
 }
 
+// Exclusive scan of cnt[0..n) for large n, in three launches: k_scan_tiles
+// scans tiles of 2048 counts (256 threads, 8 contiguous counts each) into
+// off[] and writes each tile's total; k_scan (one workgroup) scans the tile
+// totals; k_scan_add adds each tile's offset.
+constexpr int SCAN_TILE = 2048;
+
+__global__ void __launch_bounds__(256) k_scan_tiles(const int* __restrict__ cnt, int64_t n, int* __restrict__ off,
+                                                    int* __restrict__ tsum) {
+    __shared__ int sh[256];
+    const int t = threadIdx.x;
+    const int64_t base = blockIdx.x * (int64_t)SCAN_TILE + t * 8;
+    int v[8], s = 0;
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        v[i] = base + i < n ? cnt[base + i] : 0;
+        s += v[i];
+    }
+    sh[t] = s;
+    __syncthreads();
+    for (int d = 1; d < 256; d <<= 1) {   // inclusive scan of the thread sums
+        const int x = t >= d ? sh[t - d] : 0;
+        __syncthreads();
+        sh[t] += x;
+        __syncthreads();
+    }
+    int run = sh[t] - s;
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        if (base + i < n) off[base + i] = run;
+        run += v[i];
+    }
+    if (t == 255) tsum[blockIdx.x] = sh[255];
+}
+
+__global__ void __launch_bounds__(256) k_scan_add(int* __restrict__ off, int64_t n, const int* __restrict__ toff) {
+    const int64_t base = blockIdx.x * (int64_t)SCAN_TILE;
+    const int add = toff[blockIdx.x];
+    for (int64_t i = base + threadIdx.x; i < base + SCAN_TILE && i < n; i += 256) off[i] += add;
+}
+
 // --------------------------------------------------------------- screening
 // status_int[g] <- ST_ACTIVE for cells to integrate, else a final code.
 // T[i] <- T0 = T(e, Y) for every cell with a valid state.

@@ -136,6 +136,7 @@ struct chem_ctx_s {
     // workspace
     Buf st_int, active, sparse, flag, bcnt, boff, ints, ctr, save, boxes;
     Buf key, bcnt64, boff64;   // cost-ordered compaction: bucket per slot, bucket-major block counts
+    Buf scan_tmp;              // tile totals and offsets of the large scans
     // flow step: primitives, face fluxes, the Runge-Kutta stage, chemistry inputs, failure count
     Buf fQ, fF, fU1, fchem, fbad;
     hipEvent_t evf[4] = {};
@@ -189,15 +190,18 @@ int lds_blocks_per_cu(int device) {
 // addresses).
 int ensure_ws(chem_ctx_s* c, int64_t cells, size_t per_slot) {
     const int64_t nb = (cells + 255) / 256 + 1;
-    void* before[8] = {c->st_int.p, c->active.p, c->save.p, c->sparse.p, c->bcnt.p, c->key.p, c->bcnt64.p, c->boff64.p};
+    void* before[9] = {c->st_int.p, c->active.p, c->save.p, c->sparse.p, c->bcnt.p, c->key.p, c->bcnt64.p, c->boff64.p,
+                       c->scan_tmp.p};
     if (c->st_int.grow(cells) || c->active.grow(cells * 4) || c->sparse.grow(cells * 4) ||
         c->flag.grow(cells) || c->bcnt.grow(nb * 4) || c->boff.grow(nb * 4) ||
         c->ints.grow(I_COUNT * 4) || c->ctr.grow(2 * sizeof(Counters)) || c->key.grow(cells) ||
-        c->bcnt64.grow(nb * 4 * COST_BUCKETS) || c->boff64.grow(nb * 4 * COST_BUCKETS))
+        c->bcnt64.grow(nb * 4 * COST_BUCKETS) || c->boff64.grow(nb * 4 * COST_BUCKETS) ||
+        c->scan_tmp.grow(2 * 4 * (nb * COST_BUCKETS / SCAN_TILE + 2)))
         return fail(CHEM_E_NOMEM, "workspace allocation failed");
     if (c->save.grow(per_slot * (size_t)cells)) return fail(CHEM_E_NOMEM, "save-area allocation failed");
     c->cap_cells = cells;
-    void* after[8] = {c->st_int.p, c->active.p, c->save.p, c->sparse.p, c->bcnt.p, c->key.p, c->bcnt64.p, c->boff64.p};
+    void* after[9] = {c->st_int.p, c->active.p, c->save.p, c->sparse.p, c->bcnt.p, c->key.p, c->bcnt64.p, c->boff64.p,
+                      c->scan_tmp.p};
     if (memcmp(before, after, sizeof before) && c->gexec) {
         (void)hipGraphExecDestroy(c->gexec);
         c->gexec = nullptr;
@@ -228,6 +232,23 @@ SaveArea save_area(chem_ctx_s* c, int N) {
 int64_t persistent_grid(chem_ctx_s* c) {
     const int per_cu = c->opt.grid_waves > 0 ? c->opt.grid_waves : (c->m->ops ? c->m->ops->lds_blocks(c->device) : 1);
     return (int64_t)per_cu * c->ncu;
+}
+
+// Exclusive scan of n counts into off[] and their total into *total: one
+// workgroup for short arrays, the tiled three-launch scan (tile totals in
+// tmp) for long ones.
+int scan_counts(hipStream_t s, const int* cnt, int64_t n, int* off, int* total, int* tmp) {
+    if (n <= 4 * SCAN_TILE || !tmp) {
+        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, cnt, (int)n, off, total); LAUNCHED();
+        return 0;
+    }
+    const int64_t nt = (n + SCAN_TILE - 1) / SCAN_TILE;
+    int* tsum = tmp;
+    int* toff = tmp + nt + 1;
+    hipLaunchKernelGGL(k_scan_tiles, dim3(nt), dim3(256), 0, s, cnt, n, off, tsum); LAUNCHED();
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, tsum, (int)nt, toff, total); LAUNCHED();
+    hipLaunchKernelGGL(k_scan_add, dim3(nt), dim3(256), 0, s, off, n, toff); LAUNCHED();
+    return 0;
 }
 
 // phase boundary event (eager calls that return statistics only)
@@ -276,7 +297,7 @@ int pipeline_k(chem_ctx_s* c, int64_t total, int nbox, double rtol, double atol)
         hipLaunchKernelGGL((k_integrate<K, PLAIN>), dim3((total + LW - 1) / LW), dim3(64), 0, s, PK, a); LAUNCHED();
         return 0;
     }
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, c->bcnt.as<int>(), (int)nb, c->boff.as<int>(), I + I_NACT); LAUNCHED();
+    if (int rc2 = scan_counts(s, c->bcnt.as<int>(), nb, c->boff.as<int>(), I + I_NACT, c->scan_tmp.as<int>())) return rc2;
     if (o.order) {
         // cell order into a temporary list, then a stable counting sort by predicted cost
         int* tmp = c->sparse.as<int>();
@@ -284,8 +305,9 @@ int pipeline_k(chem_ctx_s* c, int64_t total, int nbox, double rtol, double atol)
                            tmp); LAUNCHED();
         hipLaunchKernelGGL((k_cost_key<M>), dim3(nb), dim3(256), 0, s, P, db, nbox, tmp, I + I_NACT, rtol, atol,
                            c->key.as<uint8_t>(), c->bcnt64.as<int>(), (int)nb); LAUNCHED();
-        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, c->bcnt64.as<int>(), (int)(nb * COST_BUCKETS),
-                           c->boff64.as<int>(), I + I_ORD); LAUNCHED();
+        if (int rc2 = scan_counts(s, c->bcnt64.as<int>(), nb * COST_BUCKETS, c->boff64.as<int>(), I + I_ORD,
+                                  c->scan_tmp.as<int>()))
+            return rc2;
         hipLaunchKernelGGL(k_bucket_scatter, dim3(nb), dim3(256), 0, s, c->key.as<uint8_t>(), tmp, I + I_NACT,
                            c->boff64.as<int>(), (int)nb, c->active.as<int>()); LAUNCHED();
     } else {
@@ -335,7 +357,7 @@ int pipeline_k(chem_ctx_s* c, int64_t total, int nbox, double rtol, double atol)
     mark(c, 1);
     hipLaunchKernelGGL(k_count_unfinished, dim3(nb), dim3(256), 0, s, c->flag.as<uint8_t>(), I + I_NACT,
                        c->bcnt.as<int>()); LAUNCHED();
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, c->bcnt.as<int>(), (int)nb, c->boff.as<int>(), I + I_NSP); LAUNCHED();
+    if (int rc2 = scan_counts(s, c->bcnt.as<int>(), nb, c->boff.as<int>(), I + I_NSP, c->scan_tmp.as<int>())) return rc2;
     hipLaunchKernelGGL(k_scatter_unfinished, dim3(nb), dim3(256), 0, s, c->flag.as<uint8_t>(), I + I_NACT,
                        c->boff.as<int>(), c->sparse.as<int>()); LAUNCHED();
     IntArgs sp = a;
