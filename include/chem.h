@@ -166,6 +166,21 @@ void chem_ctx_destroy(chem_ctx_t c);
  *                 rounds stop once a round retires less than this fraction of
  *                 the cells it started with (the active count's decay decides
  *                 the number of rounds); results do not depend on it
+ *   order         0 (default) or 1: lanes take the cells longest first.  The
+ *                 first round orders the active cells by a predicted cost, the
+ *                 number of tolerance units the state moves per dt at the start,
+ *                 dt max_i |f_i(y0)| / (rtol |y0_i| + atol), in factor-2 buckets;
+ *                 later rounds and the sparse phase take the cells the last
+ *                 round saved by their predicted remaining attempts, the round's
+ *                 pace extrapolated to t_end, att (dt - t) / (t - t_start), in
+ *                 factor-2 buckets (the per-cell completion prediction the
+ *                 paper's App. B names as the way to adapt the bulk phase).
+ *                 Results do not depend on it.  Compiled mechanisms only
+ *   kmax_adapt    0 (default, off) .. 1: each bulk round after the first takes its
+ *                 step limit from the completion predictions of the cells the
+ *                 previous round saved: the smallest power of two that covers
+ *                 this fraction of them (at least 2).  Results do not depend on
+ *                 it.  Compiled mechanisms only; ignored by the cooperative kernels
  *   method        0 = variable-order BDF (default); 1 = the paper's explicit
  *                 first-order scheme (Sec. 2.1, Alg. 2): Y <- Y + h dY/dt with h
  *                 the largest step that changes no mass fraction by more than

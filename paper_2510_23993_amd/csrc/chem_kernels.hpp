@@ -739,7 +739,77 @@ struct IntArgs {
     int kmax;
     double rtol, atol;
     Counters* ctr;
+    const int* kmax_dev;      // BULK: this round's step limit on the device (adaptive rounds), or null
+    unsigned* rem_hist;       // BULK: histogram of predicted remaining attempts of the saved cells, or null
+    uint8_t* rem_key;         // BULK: per saved slot, REM_BINS - 1 - its predicted-remaining bin, or null
 };
+
+// Completion prediction of a cell that stops at a round's step limit: the
+// attempts the rest of its interval would take at the pace of this round,
+// att_round (t_end - t) / (t - t_round_start), as a log2 bin (0 .. 31).
+constexpr int REM_BINS = 32;
+__device__ __forceinline__ int remaining_bin(int att_round, double t0, double t, double tend) {
+    const double prog = t - t0;
+    const double rem = prog > 0.0 ? att_round * (tend - t) / prog : 1e30;
+    return (int)fmin(ceil(log2(1.0 + rem)), (double)(REM_BINS - 1));
+}
+
+// Per-block counts of the cells a bulk round saved (flag 1) by their
+// completion key, bucket-major: bcnt[key * nb + block].
+__global__ void __launch_bounds__(256) k_key_count(const uint8_t* __restrict__ flag, const uint8_t* __restrict__ key,
+                                                   const int* __restrict__ n_items, int* __restrict__ bcnt, int nb) {
+    __shared__ int hist[REM_BINS];
+    const int64_t slot = blockIdx.x * 256ll + threadIdx.x;
+    if (threadIdx.x < REM_BINS) hist[threadIdx.x] = 0;
+    __syncthreads();
+    if (slot < *n_items && flag[slot] == 1) atomicAdd(&hist[key[slot] < REM_BINS ? key[slot] : REM_BINS - 1], 1);
+    __syncthreads();
+    if (threadIdx.x < REM_BINS) bcnt[threadIdx.x * nb + blockIdx.x] = hist[threadIdx.x];
+}
+
+// items[off[key * nb + block] + rank] = slot for the saved cells, rank = the
+// slot's position among the block's saved slots of that key: a stable
+// counting sort, most remaining work first.
+__global__ void __launch_bounds__(256) k_key_scatter(const uint8_t* __restrict__ flag, const uint8_t* __restrict__ key,
+                                                     const int* __restrict__ n_items, const int* __restrict__ off,
+                                                     int nb, int* __restrict__ items) {
+    __shared__ int wc[4][REM_BINS];
+    const int64_t slot = blockIdx.x * 256ll + threadIdx.x;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int b = (slot < *n_items && flag[slot] == 1) ? (key[slot] < REM_BINS ? key[slot] : REM_BINS - 1) : -1;
+    int within = 0;
+    for (int bb = 0; bb < REM_BINS; bb++) {
+        const unsigned long long m = wave_ballot(b == bb);
+        if (b == bb) within = __popcll(m & ((1ull << lane) - 1ull));
+        if (lane == 0) wc[w][bb] = __popcll(m);
+    }
+    __syncthreads();
+    if (b >= 0) {
+        int before = 0;
+        for (int q = 0; q < w; q++) before += wc[q][b];
+        items[off[b * nb + blockIdx.x] + before + within] = (int)slot;
+    }
+}
+
+// Step limit of the next bulk round from the predictions of the cells the
+// last round saved: the smallest 2^b that covers a fraction q of them,
+// clamped to [kmin, kcap] (kmin when no cell was saved).
+__global__ void k_next_kmax(const unsigned* __restrict__ hist, const int* __restrict__ saved, double q, int kmin,
+                            int kcap, int* __restrict__ kmax) {
+    if (threadIdx.x != 0) return;
+    const double need = q * (double)*saved;
+    double cum = 0.0;
+    int b = REM_BINS - 1;
+    for (int i = 0; i < REM_BINS; i++) {
+        cum += hist[i];
+        if (cum >= need) {
+            b = i;
+            break;
+        }
+    }
+    const double k = *saved > 0 ? ldexp(1.0, b) : (double)kmin;
+    *kmax = (int)fmin(fmax(k, (double)kmin), (double)kcap);
+}
 
 template <class M, int MODE>
 __global__ void __launch_bounds__(64) k_integrate(const Params<M>* __restrict__ Pp, IntArgs a) {
@@ -756,11 +826,13 @@ __global__ void __launch_bounds__(64) k_integrate(const Params<M>* __restrict__ 
         if (a.gate_prev && (double)*a.gate > a.keep * (double)*a.gate_prev) return;
         if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(a.rounds, 1);
     }
+    const int kmax = (MODE == BULK && a.kmax_dev) ? *a.kmax_dev : a.kmax;
     const int64_t n_items = (MODE == PLAIN) ? a.n_items_host : (int64_t)*a.n_items_dev;
     double D[ND][N];
 
     Lane<M> L;
     L.n_steps = L.n_att = L.n_rhs = L.n_jac = L.n_lu = L.n_solve = 0;
+    double t_round0 = 0.0;   // the cell's time when this round took it
     unsigned long long max_att = 0, incomplete = 0, unfinished = 0;
     int64_t cur = -1;     // current item
     int slot = -1;
@@ -790,7 +862,7 @@ __global__ void __launch_bounds__(64) k_integrate(const Params<M>* __restrict__ 
                 if (need) {
                     const int my = base + __popcll(m & ((1ull << lane) - 1ull));
                     if (my < n_items) {
-                        const int s = (MODE == SPARSE) ? a.items[my] : my;
+                        const int s = (MODE == SPARSE || a.items) ? a.items[my] : my;
                         if (a.flag[s] != 2) {
                             cur = my;
                             slot = s;
@@ -837,6 +909,7 @@ __global__ void __launch_bounds__(64) k_integrate(const Params<M>* __restrict__ 
                 y0[NS] = B.T[i];
                 bdf_init(P, L, D, y0, a.rtol, a.atol);
             }
+            t_round0 = L.t;
         }
         // ---- one step attempt
         const int r = bdf_attempt(P, L, D, A, a.rtol, a.atol);
@@ -847,7 +920,7 @@ __global__ void __launch_bounds__(64) k_integrate(const Params<M>* __restrict__ 
         } else if (r == SR_FAIL) {
             finished = true;
             st = ST_FAIL;
-        } else if (L.round_att >= a.kmax) {
+        } else if (L.round_att >= kmax) {
             if (MODE == BULK) save = true;
             else {
                 finished = true;
@@ -885,6 +958,11 @@ __global__ void __launch_bounds__(64) k_integrate(const Params<M>* __restrict__ 
                 S.ints[3 * S.ld + slot] = (L.lu_ok ? 1 : 0) | (L.jac_fresh ? 2 : 0) | (L.last ? 4 : 0);
                 a.flag[slot] = 1;
                 unfinished++;
+                if (MODE == BULK && (a.rem_hist || a.rem_key)) {
+                    const int bin = remaining_bin(L.round_att, t_round0, L.t, L.tend);
+                    if (a.rem_hist) atomicAdd(&a.rem_hist[bin], 1u);
+                    if (a.rem_key) a.rem_key[slot] = (uint8_t)(REM_BINS - 1 - bin);
+                }
             }
             cur = -1;
             g = -1;

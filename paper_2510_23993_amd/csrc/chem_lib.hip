@@ -53,7 +53,10 @@ int fail(int code, const std::string& msg) {
 constexpr int RMAX = 64;  // most bulk-round launches per pipeline
 constexpr double EXPLICIT_Y_FLOOR = 1e-10;   // floor under the explicit scheme's relative step limit
 // device int counters
-enum { I_NACT = 0, I_NSP = 1, I_ROUNDS = 2, I_ORD = 3, I_Q = 4, I_UNF = I_Q + RMAX + 2, I_COUNT = I_UNF + RMAX };
+// device ints: counts, queues, per-round unfinished counts, per-round step
+// limits and completion histograms of the adaptive rounds
+enum { I_NACT = 0, I_NSP = 1, I_ROUNDS = 2, I_ORD = 3, I_Q = 4, I_UNF = I_Q + RMAX + 2, I_KR = I_UNF + RMAX,
+       I_HIST = I_KR + RMAX + 1, I_COUNT = I_HIST + RMAX * REM_BINS };
 
 struct Options {
     int algorithm = 1;
@@ -72,6 +75,7 @@ struct Options {
     int method = 0;           // 0 = variable-order BDF, 1 = the explicit first-order scheme
     double explicit_frac = 0.01;  // explicit scheme: largest relative change of a mass fraction per step
     int order = 0;            // 1 = lanes take the active cells in predicted-cost order, longest first
+    double kmax_adapt = 0.0;  // > 0: each bulk round's step limit covers this fraction of the predicted completions
     bool operator==(const Options& o) const { return !memcmp(this, &o, sizeof(Options)); }
 };
 
@@ -137,6 +141,7 @@ struct chem_ctx_s {
     Buf st_int, active, sparse, flag, bcnt, boff, ints, ctr, save, boxes;
     Buf key, bcnt64, boff64;   // cost-ordered compaction: bucket per slot, bucket-major block counts
     Buf scan_tmp;              // tile totals and offsets of the large scans
+    Buf items2;                // second item list of the ordered bulk rounds
     // flow step: primitives, face fluxes, the Runge-Kutta stage, chemistry inputs, failure count
     Buf fQ, fF, fU1, fchem, fbad;
     hipEvent_t evf[4] = {};
@@ -190,18 +195,18 @@ int lds_blocks_per_cu(int device) {
 // addresses).
 int ensure_ws(chem_ctx_s* c, int64_t cells, size_t per_slot) {
     const int64_t nb = (cells + 255) / 256 + 1;
-    void* before[9] = {c->st_int.p, c->active.p, c->save.p, c->sparse.p, c->bcnt.p, c->key.p, c->bcnt64.p, c->boff64.p,
-                       c->scan_tmp.p};
+    void* before[10] = {c->st_int.p, c->active.p, c->save.p, c->sparse.p, c->bcnt.p, c->key.p, c->bcnt64.p, c->boff64.p,
+                        c->scan_tmp.p, c->items2.p};
     if (c->st_int.grow(cells) || c->active.grow(cells * 4) || c->sparse.grow(cells * 4) ||
         c->flag.grow(cells) || c->bcnt.grow(nb * 4) || c->boff.grow(nb * 4) ||
         c->ints.grow(I_COUNT * 4) || c->ctr.grow(2 * sizeof(Counters)) || c->key.grow(cells) ||
         c->bcnt64.grow(nb * 4 * COST_BUCKETS) || c->boff64.grow(nb * 4 * COST_BUCKETS) ||
-        c->scan_tmp.grow(2 * 4 * (nb * COST_BUCKETS / SCAN_TILE + 2)))
+        c->scan_tmp.grow(2 * 4 * (nb * COST_BUCKETS / SCAN_TILE + 2)) || c->items2.grow(cells * 4))
         return fail(CHEM_E_NOMEM, "workspace allocation failed");
     if (c->save.grow(per_slot * (size_t)cells)) return fail(CHEM_E_NOMEM, "save-area allocation failed");
     c->cap_cells = cells;
-    void* after[9] = {c->st_int.p, c->active.p, c->save.p, c->sparse.p, c->bcnt.p, c->key.p, c->bcnt64.p, c->boff64.p,
-                      c->scan_tmp.p};
+    void* after[10] = {c->st_int.p, c->active.p, c->save.p, c->sparse.p, c->bcnt.p, c->key.p, c->bcnt64.p, c->boff64.p,
+                       c->scan_tmp.p, c->items2.p};
     if (memcmp(before, after, sizeof before) && c->gexec) {
         (void)hipGraphExecDestroy(c->gexec);
         c->gexec = nullptr;
@@ -342,26 +347,67 @@ int pipeline_k(chem_ctx_s* c, int64_t total, int nbox, double rtol, double atol)
         return 0;
     }
     const int rounds = std::min(o.max_rounds, RMAX);
+    const bool adapt = o.kmax_adapt > 0.0;
+    if (adapt) {   // round 0 runs kmax_bulk steps; later rounds take the limit from the last round's predictions
+        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, I + I_KR, (int64_t)1, o.kmax_bulk); LAUNCHED();
+    }
+    // with cost ordering, the rounds after the first and the sparse phase take
+    // the cells the last round saved, most predicted remaining work first
+    int* lists[2] = {c->sparse.as<int>(), c->items2.as<int>()};
+    auto ordered_list = [&](int* out) -> int {
+        hipLaunchKernelGGL(k_key_count, dim3(nb), dim3(256), 0, s, c->flag.as<uint8_t>(), c->key.as<uint8_t>(),
+                           I + I_NACT, c->bcnt64.as<int>(), (int)nb); LAUNCHED();
+        if (int rc2 = scan_counts(s, c->bcnt64.as<int>(), nb * REM_BINS, c->boff64.as<int>(), I + I_NSP,
+                                  c->scan_tmp.as<int>()))
+            return rc2;
+        hipLaunchKernelGGL(k_key_scatter, dim3(nb), dim3(256), 0, s, c->flag.as<uint8_t>(), c->key.as<uint8_t>(),
+                           I + I_NACT, c->boff64.as<int>(), (int)nb, out); LAUNCHED();
+        return 0;
+    };
     mark(c, 0);
     for (int r = 0; r < rounds; r++) {
         IntArgs b = a;
         b.n_items_dev = I + I_NACT;
+        if (o.order) {
+            b.rem_key = c->key.as<uint8_t>();
+            if (r > 0) {
+                b.items = lists[(r - 1) & 1];
+                b.n_items_dev = I + I_UNF + r - 1;
+            }
+        }
         b.queue = I + I_Q + r;
         b.unfinished = I + I_UNF + r;
         b.gate = r == 0 ? I + I_NACT : I + I_UNF + r - 1;
         b.gate_prev = r == 0 ? nullptr : (r == 1 ? I + I_NACT : I + I_UNF + r - 2);
         b.keep = 1.0 - o.round_decay;
         b.kmax = o.kmax_bulk;
+        if (adapt) {
+            b.kmax_dev = I + I_KR + r;
+            b.rem_hist = (unsigned*)(I + I_HIST + r * REM_BINS);
+        }
         hipLaunchKernelGGL((k_integrate<K, BULK>), dim3(grid), dim3(64), 0, s, PK, b); LAUNCHED();
+        if (o.order) {
+            if (int rc2 = ordered_list(lists[r & 1])) return rc2;
+        }
+        if (adapt && r + 1 < rounds) {
+            hipLaunchKernelGGL(k_next_kmax, dim3(1), dim3(64), 0, s, (const unsigned*)(I + I_HIST + r * REM_BINS),
+                               I + I_UNF + r, o.kmax_adapt, 2, 1 << 20, I + I_KR + r + 1); LAUNCHED();
+        }
     }
     mark(c, 1);
-    hipLaunchKernelGGL(k_count_unfinished, dim3(nb), dim3(256), 0, s, c->flag.as<uint8_t>(), I + I_NACT,
-                       c->bcnt.as<int>()); LAUNCHED();
-    if (int rc2 = scan_counts(s, c->bcnt.as<int>(), nb, c->boff.as<int>(), I + I_NSP, c->scan_tmp.as<int>())) return rc2;
-    hipLaunchKernelGGL(k_scatter_unfinished, dim3(nb), dim3(256), 0, s, c->flag.as<uint8_t>(), I + I_NACT,
-                       c->boff.as<int>(), c->sparse.as<int>()); LAUNCHED();
+    int* sparse_list = c->sparse.as<int>();
+    if (o.order && rounds > 0) {
+        sparse_list = lists[(rounds - 1) & 1];   // built after the last round (I_NSP holds its length)
+    } else {
+        hipLaunchKernelGGL(k_count_unfinished, dim3(nb), dim3(256), 0, s, c->flag.as<uint8_t>(), I + I_NACT,
+                           c->bcnt.as<int>()); LAUNCHED();
+        if (int rc2 = scan_counts(s, c->bcnt.as<int>(), nb, c->boff.as<int>(), I + I_NSP, c->scan_tmp.as<int>()))
+            return rc2;
+        hipLaunchKernelGGL(k_scatter_unfinished, dim3(nb), dim3(256), 0, s, c->flag.as<uint8_t>(), I + I_NACT,
+                           c->boff.as<int>(), c->sparse.as<int>()); LAUNCHED();
+    }
     IntArgs sp = a;
-    sp.items = c->sparse.as<int>();
+    sp.items = sparse_list;
     sp.n_items_dev = I + I_NSP;
     sp.queue = I + I_Q + RMAX;
     sp.kmax = o.kmax_sparse;
@@ -1249,6 +1295,10 @@ int chem_set_option(chem_ctx_t c, const char* key, double v) {
         o.surrogate = (int)v;
     } else if (k == "surr_rtol" && in(1e-12, 1.0)) o.surr_rtol = v;
     else if (k == "round_decay" && in(0.0, 0.99)) o.round_decay = v;
+    else if (k == "kmax_adapt" && in(0.0, 1.0)) {
+        if (v > 0 && !c->m->ops) return fail(CHEM_E_INVAL, "adaptive rounds need a compiled mechanism");
+        o.kmax_adapt = v;
+    }
     else if (k == "method" && (v == 0 || v == 1)) {
         if (v == 1 && !c->m->ops) return fail(CHEM_E_INVAL, "the explicit scheme needs a compiled mechanism");
         o.method = (int)v;
@@ -1281,6 +1331,7 @@ int chem_get_option(chem_ctx_t c, const char* key, double* v) {
     else if (k == "surrogate") *v = o.surrogate;
     else if (k == "surr_rtol") *v = o.surr_rtol;
     else if (k == "round_decay") *v = o.round_decay;
+    else if (k == "kmax_adapt") *v = o.kmax_adapt;
     else if (k == "method") *v = o.method;
     else if (k == "explicit_frac") *v = o.explicit_frac;
     else if (k == "order") *v = o.order;

@@ -150,7 +150,12 @@ def test_bulk_sparse_bitwise_equals_plain(chem, mech, m9, group):
                  {"algorithm": 1, "max_rounds": 0},
                  # lanes take the cells in predicted-cost order (longest first)
                  {"algorithm": 1, "max_rounds": 0, "order": 1},
-                 {"algorithm": 1, "nactive_star": 0, "kmax_bulk": 3, "order": 1}):
+                 {"algorithm": 1, "nactive_star": 0, "kmax_bulk": 3, "order": 1},
+                 # later rounds and the sparse phase in predicted-remaining order, and
+                 # step limits set from the completion predictions
+                 {"algorithm": 1, "nactive_star": 500, "kmax_bulk": 3, "order": 1},
+                 {"algorithm": 1, "nactive_star": 0, "kmax_bulk": 2, "kmax_adapt": 0.5},
+                 {"algorithm": 1, "nactive_star": 300, "kmax_bulk": 4, "order": 1, "kmax_adapt": 0.75}):
         ctx = chem.Context(mech, t_react_min=0.0, group=group, **opts)
         Yg, Tg, st, stats = run_gpu(ctx, rho, e, c.Y, c.T, c.dt, RTOL_C1, ATOL_C1)
         assert np.all(st == 0)

@@ -160,3 +160,28 @@ def test_full_size_evaluation_field_within_budget(chem, mech, m9, weights):
     print(f"8.4M-cell field: accepted {ok.size}, fell back {rej.size}, {st['t_total_ms']:.1f} ms; "
           f"{idx.size} sampled: max rel {rel.max():.2e}, max |dT| {dT.max():.2e} K")
     assert rel.max() <= BUDGET_REL and dT.max() <= BUDGET_T
+
+
+def test_trust_check_rejects_every_prediction_over_budget(chem, mech, m9, weights):
+    """The budget check with the accept path exercised: at the loosest trust
+    tolerance (1.0) the network's own end states are written for every cell
+    that passes the envelope, positivity and temperature checks; sampled ones
+    are measured against the oracle.  Every sampled cell whose prediction
+    misses the 1e-4 / 1 K budget must be rejected at the default trust
+    tolerance, and any sampled cell accepted there must meet the budget."""
+    c = fields.c2_field(256, 24, 2, seed=1005)
+    rho, e = oracle_inputs(m9, c)
+    Yp, Tp, s_loose, st_loose = _run(chem, mech, c, rho, e, weights, 1.0)
+    _, _, s_def, st_def = _run(chem, mech, c, rho, e, weights)
+    ok = np.where(s_loose == chem.ST_SURR_OK)[0]
+    assert ok.size > 0.5 * (c.cls > 0).sum()   # the accept path ran on most active cells
+    idx = ok[:: max(1, ok.size // 300)].astype(np.int64)
+    rel, dT = _errors(m9, c, rho, e, Yp, Tp, idx)
+    over = (rel > BUDGET_REL) | (dT > BUDGET_T)
+    print(f"network predictions on {idx.size} cells: relative species error median {np.median(rel):.2e}, "
+          f"90% {np.quantile(rel, 0.9):.2e}, max {rel.max():.2e}; |dT| median {np.median(dT):.2e} K; "
+          f"within budget {np.mean(~over):.3f}; accepted at the default trust: {st_def['n_surrogate']}")
+    assert np.all(s_def[idx[over]] == chem.ST_SURR_REJ)
+    acc = idx[s_def[idx] == chem.ST_SURR_OK]
+    if acc.size:
+        assert not np.any(over[np.isin(idx, acc)])
