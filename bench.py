@@ -249,7 +249,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the AMR and surrogate configurations")
     ap.add_argument("--opt", action="append", default=[], help="key=value library option (skips autotuning)")
     ap.add_argument("--rtol", type=float, default=0.0, help="fixed rtol (0: the fixed-error sweep)")
-    ap.add_argument("--workload", default="detonation", choices=["detonation", "amr", "m53", "strang"])
+    ap.add_argument("--workload", default="detonation", choices=["detonation", "amr", "m53", "strang", "contract"])
     ap.add_argument("--cells", type=int, default=65536, help="m53 workload: cells")
     ap.add_argument("--chunks", type=int, default=1, help="m53 workload: calls the cells are split into")
     ap.add_argument("--traffic-probe", action="store_true", help=argparse.SUPPRESS)
@@ -276,6 +276,8 @@ def main():
         return bench_m53(args, torch, chem, fields, oracle)
     if args.workload == "strang":
         return bench_strang(args, torch, chem, fields)
+    if args.workload == "contract":
+        return bench_contract(args, torch, chem, fields)
 
     log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
     mech = chem.Mechanism(fields.M9_PATH)
@@ -668,6 +670,42 @@ def bench_strang(args, torch, chem, fields):
 
 
 # ------------------------------------------------------------ 53 species
+def bench_contract(args, torch, chem, fields):
+    """The stoichiometric contractions of the matrix-form rates alone
+    (chem_eval_contractions) on batches of states, FP64 and FP32 sparse loops
+    against the BF16 matrix cores with the three-term split: 8,388,608
+    states of the 9-species mechanism and 1,048,576 of the 53-species one,
+    ln C uniform in [-45, 8]; median of 5 launches each (HIP events)."""
+    out = {"workload": "stoichiometric contractions nu'^T ln C and nu''^T ln C", "runs": []}
+    for path, n in ((fields.M9_PATH, 1 << 23), (fields.M53_PATH, 1 << 20)):
+        mech = chem.Mechanism(path)
+        ctx = chem.Context(mech)
+        g = torch.Generator(device="cuda").manual_seed(7)
+        lnC = torch.rand((mech.ns, n), dtype=torch.float64, device="cuda", generator=g) * 53.0 - 45.0
+        zf = torch.empty((mech.nr, n), dtype=torch.float64, device="cuda")
+        zr = torch.empty_like(zf)
+        kt, nt = (mech.ns + 31) // 32, (2 * mech.nr + 15) // 16
+        for prec in (0, 1, 2):
+            ms = []
+            for _ in range(6):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                ctx.eval_contractions(lnC, zf, zr, prec)
+                e1.record()
+                torch.cuda.synchronize()
+                ms.append(e0.elapsed_time(e1))
+            t = float(np.median(ms[1:]))
+            row = {"nspec": mech.ns, "nreac": mech.nr, "states": n, "precision": prec, "ms": t,
+                   "ns_per_state": t * 1e6 / n,
+                   "hbm_bytes": 8 * n * (mech.ns + 2 * mech.nr),
+                   "hbm_GBps": 8 * n * (mech.ns + 2 * mech.nr) / (t * 1e-3) / 1e9}
+            if prec == 2:
+                issued = 2.0 * 16 * 16 * 32 * 3 * kt * nt * (n / 16)
+                row["mfma_issued_TFLOPs"] = issued / (t * 1e-3) / 1e12
+            out["runs"].append(row)
+    print(json.dumps(out))
+
+
 def bench_m53(args, torch, chem, fields, oracle):
     """53-species / 325-reaction mechanism, n cells of the seeded T/p/progress
     distribution, dt 1e-7 s, FP64 at rtol 1e-7 / atol 1e-20 (the loosest

@@ -282,6 +282,21 @@ int chem_prepare_state(chem_ctx_t c, int64_t ncell, const double* T, const doubl
 int chem_eval_rhs(chem_ctx_t c, int64_t ncell, const double* rho, const double* y, double* f,
                   double* J);
 
+/* Stoichiometric contractions of the matrix-form rate evaluation (Sec. 2.1,
+ * rates of progress as contractions of the stoichiometric matrices with
+ * log-concentrations, then exp) as a batch operation: for n states given as
+ * lnC [nspec][n] (ln|C_k| in ln(mol/m^3), column-major, device),
+ *   zf[j][i] = sum_k nu'_kj lnC[k][i],  zr[j][i] = sum_k nu''_kj lnC[k][i]
+ * for every reaction j (outputs [nreac][n] each, device, FP64).
+ *   precision 0: FP64 loops over each reaction's participants;
+ *             1: the same loops in FP32;
+ *             2: dense BF16 matrix cores, ln C split into three BF16 terms
+ *                (about 24 significant bits), integer coefficients exact,
+ *                FP32 accumulation; at most 128 species.
+ * Asynchronous.  CHEM_E_INVAL for bad arguments, CHEM_E_MECH when the
+ * mechanism is too large for the matrix-core variant. */
+int chem_eval_contractions(chem_ctx_t c, int64_t n, const double* lnC, double* zf, double* zr, int precision);
+
 /* Autotuner: times candidate schedules (lanes per cell, bulk phase on/off,
  * N*, steps per bulk round, persistent grid size) on the given boxes and sets the fastest as the
  * context's options.  Y and T of every box are restored afterwards (the call

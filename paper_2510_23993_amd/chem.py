@@ -56,7 +56,8 @@ EXPORTS = ["chem_load_mechanism", "chem_mech_info", "chem_species_name", "chem_f
            "chem_mlp_nparams", "chem_mlp_workspace_floats", "chem_mlp_forward", "chem_mlp_backward",
            "chem_mlp_mse", "chem_mlp_adam", "chem_mlp_gather", "chem_mlp_colstats", "chem_mlp_standardize",
            "chem_mlp_colrange", "chem_surrogate_pairs", "chem_mech_hash",
-           "chem_flow_step", "chem_strang_step", "chem_integrate_noalloc"]
+           "chem_flow_step", "chem_strang_step", "chem_integrate_noalloc",
+           "chem_eval_contractions"]
 
 
 def lib():
@@ -87,6 +88,7 @@ def lib():
     L.chem_integrate.argtypes = [vp, i64, vp, vp, vp, i64, vp, vp, vp, dbl, dbl, dbl,
                                  C.POINTER(chem_stats)]
     L.chem_integrate_noalloc.argtypes = [vp, i64, vp, vp, vp, i64, vp, vp, vp, dbl, dbl, dbl]
+    L.chem_eval_contractions.argtypes = [vp, i64, vp, vp, vp, C.c_int]
     L.chem_integrate_boxes.argtypes = [vp, C.c_int, C.POINTER(chem_box), dbl, dbl, C.POINTER(chem_stats)]
     L.chem_flow_step.argtypes = [vp, i64, dbl, dbl, vp, i64, vp]
     L.chem_strang_step.argtypes = [vp, i64, dbl, dbl, vp, i64, vp, vp, dbl, dbl, C.POINTER(chem_stats)]
@@ -295,6 +297,15 @@ class Context:
     def eval_rhs(self, rho, y, f, J=None):
         n = rho.shape[0]
         _check(lib().chem_eval_rhs(self._h, n, _ptr(rho), _ptr(y), _ptr(f), _ptr(J)))
+
+    def eval_contractions(self, lnC, zf, zr, precision=0):
+        """chem_eval_contractions: zf = nu'^T lnC and zr = nu''^T lnC for n
+        states; lnC [ns, n], zf and zr [nr, n] float64 device tensors."""
+        n = lnC.shape[1]
+        _check_f64("lnC", lnC, (self.mech.ns, n))
+        _check_f64("zf", zf, (self.mech.nr, n))
+        _check_f64("zr", zr, (self.mech.nr, n))
+        _check(lib().chem_eval_contractions(self._h, n, _ptr(lnC), _ptr(zf), _ptr(zr), int(precision)))
 
     def synchronize(self):
         _check(lib().chem_synchronize(self._h))

@@ -17,6 +17,7 @@
 #include "chem_host_mech.hpp"
 #include "chem_params.hpp"
 #include "chem_coop.hpp"
+#include "chem_contract.hpp"
 #include "chem_flow.hpp"
 #include "chem_kernels.hpp"
 #include "chem_mlp.hpp"
@@ -127,6 +128,7 @@ struct chem_mech_s {
     const MechOps* ops = nullptr;   // compiled one-lane kernels for this structure (may be null)
     void* dparams = nullptr;
     CoopMech cm{};                  // data-driven device tables (every mechanism)
+    ContractTables ct{};            // stoichiometric matrices of the batch contractions
     std::vector<void*> dbufs;
     int device = 0;
 };
@@ -447,6 +449,64 @@ int eval(chem_ctx_s* c, int64_t n, const double* rho, const double* y, double* f
 
 
 // ------------------------------------------------------- data-driven tables
+// Tables of chem_eval_contractions: participant lists of the 2 nr columns
+// (nu'_.j, nu''_.j) and the same matrix as BF16 B fragments of the matrix
+// cores (exact small integers), species padded to 32, columns to 16.
+int upload_contract_tables(chem_mech_s* m) {
+    const HostMech& h = m->hm;
+    const int ns = h.ns, nr = (int)h.rx.size(), ncol = 2 * nr;
+    std::vector<int> ptr(ncol + 1, 0), sp, nu;
+    auto coef = [&](int c, int k) {   // coefficient of species k in column c
+        const auto& lst = (c & 1) ? h.rx[c >> 1].pr : h.rx[c >> 1].re;
+        int v = 0;
+        for (const auto& pr : lst)
+            if (pr.first == k) v += pr.second;
+        return v;
+    };
+    for (int col = 0; col < ncol; col++) {
+        for (int k = 0; k < ns; k++) {
+            const int v = coef(col, k);
+            if (v) {
+                sp.push_back(k);
+                nu.push_back(v);
+            }
+        }
+        ptr[col + 1] = (int)sp.size();
+    }
+    if (sp.empty()) {
+        sp.push_back(0);
+        nu.push_back(0);
+    }
+    const int kt = (ns + 31) / 32, nt = std::max(1, (ncol + 15) / 16);
+    std::vector<uint16_t> frag((size_t)kt * nt * 64 * 8, 0);
+    for (int kb = 0; kb < kt; kb++)
+        for (int nb = 0; nb < nt; nb++)
+            for (int l = 0; l < 64; l++)
+                for (int e = 0; e < 8; e++) {
+                    const int k = kb * 32 + 8 * (l / 16) + e, col = nb * 16 + l % 16;
+                    const int v = (k < ns && col < ncol) ? coef(col, k) : 0;
+                    // small integers are exact in BF16: the top half of their FP32 pattern
+                    const float f = (float)v;
+                    uint32_t u;
+                    memcpy(&u, &f, 4);
+                    frag[(((size_t)kb * nt + nb) * 64 + l) * 8 + e] = (uint16_t)(u >> 16);
+                }
+    auto up = [&](const void* src, size_t bytes, void** dst) -> int {
+        void* d = nullptr;
+        HIPCHK(hipMalloc(&d, bytes));
+        m->dbufs.push_back(d);
+        HIPCHK(hipMemcpy(d, src, bytes, hipMemcpyHostToDevice));
+        *dst = d;
+        return 0;
+    };
+    void *a1, *a2, *a3, *a4;
+    if (up(ptr.data(), ptr.size() * 4, &a1) || up(sp.data(), sp.size() * 4, &a2) || up(nu.data(), nu.size() * 4, &a3) ||
+        up(frag.data(), frag.size() * 2, &a4))
+        return CHEM_E_HIP;
+    m->ct = ContractTables{ns, nr, (const int*)a1, (const int*)a2, (const int*)a3, (const bf16x8*)a4, kt, nt};
+    return 0;
+}
+
 int upload_coop_tables(chem_mech_s* m) {
     const HostMech& h = m->hm;
     const int ns = h.ns, nr = (int)h.rx.size();
@@ -619,6 +679,7 @@ int coop_lds_init(int device) {
         set((const void*)k_eval_coop<g, r>);
         CHEM_COOP_SCHEDULES(X)
 #undef X
+        set((const void*)k_contract_mfma);
         g_lds_max[device] = v;
     });
     if (err != hipSuccess) return fail(CHEM_E_HIP, std::string("LDS limit of the cooperative kernels: ") + hipGetErrorString(err));
@@ -1203,6 +1264,7 @@ int chem_load_mechanism(const char* path, chem_mech_t* out) {
     int rc = ops ? ops->upload(m->hm, &m->dparams) : 0;
     if (rc) return rc;
     rc = upload_coop_tables(m.get());
+    if (!rc) rc = upload_contract_tables(m.get());
     if (rc) {
         for (void* p : m->dbufs) (void)hipFree(p);
         if (m->dparams) (void)hipFree(m->dparams);
@@ -1467,6 +1529,28 @@ int chem_surrogate_pairs(chem_ctx_t c, int64_t n, const double* rho, const doubl
 int chem_mech_hash(chem_mech_t m, uint64_t* hash) {
     if (!m || !hash) return fail(CHEM_E_INVAL, "NULL argument");
     *hash = m->hm.hash;
+    return 0;
+}
+
+int chem_eval_contractions(chem_ctx_t c, int64_t n, const double* lnC, double* zf, double* zr, int precision) {
+    if (!c) return fail(CHEM_E_INVAL, "NULL context");
+    if (n < 0 || precision < 0 || precision > 2) return fail(CHEM_E_INVAL, "n < 0 or precision not 0, 1 or 2");
+    if (n == 0) return 0;
+    if (!lnC || !zf || !zr) return fail(CHEM_E_INVAL, "NULL array");
+    const ContractTables& t = c->m->ct;
+    HIPCHK(hipSetDevice(c->device));
+    const int64_t grid = std::min<int64_t>((n + 255) / 256, (int64_t)c->ncu * 16);
+    if (precision == 0) {
+        hipLaunchKernelGGL(k_contract_sparse<double>, dim3(grid), dim3(256), 0, c->stream, t, n, lnC, zf, zr); LAUNCHED();
+    } else if (precision == 1) {
+        hipLaunchKernelGGL(k_contract_sparse<float>, dim3(grid), dim3(256), 0, c->stream, t, n, lnC, zf, zr); LAUNCHED();
+    } else {
+        if (t.kt > CONTRACT_KTMAX) return fail(CHEM_E_MECH, "more than 128 species for the matrix-core contraction");
+        const int lds = t.kt * t.nt * 64 * (int)sizeof(bf16x8);
+        if (lds > g_lds_max[c->device]) return fail(CHEM_E_MECH, "contraction matrix larger than the LDS of a workgroup");
+        const int64_t g2 = std::min<int64_t>((n + 63) / 64, (int64_t)c->ncu * 8);
+        hipLaunchKernelGGL(k_contract_mfma, dim3(g2), dim3(256), lds, c->stream, t, n, lnC, zf, zr); LAUNCHED();
+    }
     return 0;
 }
 
