@@ -332,7 +332,9 @@ __global__ void k_eval_rhs(const Params<M>* __restrict__ Pp, int64_t n, const do
 // Jacobian from an earlier step), local error d/(k+1), WRMS norm with
 // weights 1/(rtol |y| + atol).  The Newton convergence test, the update of
 // the differences on acceptance and the order selection follow SciPy's BDF
-// implementation (scipy/integrate/_ivp/bdf.py, BSD-3-Clause).  The
+// implementation (scipy/integrate/_ivp/bdf.py, BSD-3-Clause), except that
+// the first Newton iteration may already converge on the contraction
+// estimate carried from earlier attempts (Hairer & Wanner's RADAU5 rule).  The
 // differences D[j][i] (j = 0..MAXORD+2) live in the lane's registers: every
 // access below uses indices that are compile-time constants once the loops
 // are unrolled (the order k only selects among them).
@@ -351,6 +353,7 @@ template <class M>
 struct Lane {
     static constexpr int N = M::N;
     double t, tend, h, c_lu, rho;
+    double eta;   // Newton contraction estimate theta/(1 - theta) carried between attempts
     int k, neq, att, round_att;
     bool lu_ok, jac_fresh, last;   // last: the next attempt ends on t_end
     int piv[M::NN];
@@ -546,7 +549,12 @@ __device__ __forceinline__ int bdf_attempt(const Params<M>& P, Lane<M>& L, doubl
                 yn[i] += f[i];
                 d[i] += f[i];
             }
-            if (dn == 0.0 || (rate >= 0.0 && rate / (1.0 - rate) * dn < tol)) {
+            // the first iteration may converge on the contraction estimate of
+            // the previous attempts, eta^0.8 (the rule of Hairer & Wanner's
+            // RADAU5); later ones on this attempt's own rate
+            const double eta = rate >= 0.0 ? rate / (1.0 - rate) : exp2(0.8 * log2(fmax(L.eta, 1e-16)));
+            if (rate >= 0.0) L.eta = eta;
+            if (dn == 0.0 || eta * dn < tol) {
                 conv = true;
                 break;
             }
@@ -706,6 +714,7 @@ __device__ __forceinline__ void bdf_init(const Params<M>& P, Lane<M>& L, double 
     L.lu_ok = false;
     L.jac_fresh = false;
     L.c_lu = 0.0;
+    L.eta = 1.0;
     L.last = L.h >= L.tend;   // t = 0: the first step covers the interval
 }
 
@@ -713,7 +722,7 @@ __device__ __forceinline__ void bdf_init(const Params<M>& P, Lane<M>& L, double 
 struct SaveArea {             // per active slot, lane-major [field][slot]
     double* D;                // ND * N rows
     double* LU;               // N * N rows
-    double* scal;             // 4 rows: t, h, c_lu, (unused)
+    double* scal;             // 4 rows: t, h, c_lu, eta
     int* ints;                // 4 rows: k, neq, att, flags(lu_ok | jac_fresh<<1 | last<<2)
     int8_t* piv;              // N rows
     int64_t ld;               // capacity (slots)
@@ -811,6 +820,8 @@ __global__ void k_next_kmax(const unsigned* __restrict__ hist, const int* __rest
     *kmax = (int)fmin(fmax(k, (double)kmin), (double)kcap);
 }
 
+constexpr int REFILL_MIN = 24;
+
 template <class M, int MODE>
 __global__ void __launch_bounds__(64) k_integrate(const Params<M>* __restrict__ Pp, IntArgs a) {
     constexpr int N = M::N, NS = M::NS;
@@ -850,7 +861,13 @@ __global__ void __launch_bounds__(64) k_integrate(const Params<M>* __restrict__ 
                 if (lane < LW && it < n_items && a.st_int[it] == ST_ACTIVE) cur = it;
             }
         } else {
-            for (;;) {
+            // lanes refill together: a wave takes new cells once REFILL_MIN of
+            // its lanes are free (or none is busy), so the starting steps of
+            // new cells, which every lane of the wave executes, run for many
+            // cells at once instead of for one or two per attempt
+            const bool refill = wave_ballot(cur >= 0) == 0 ||
+                                __popcll(wave_ballot(cur < 0 && !exhausted)) >= REFILL_MIN;
+            for (; refill;) {
                 const bool need = cur < 0 && !exhausted;
                 const unsigned long long m = wave_ballot(need);
                 if (!m) break;
@@ -895,6 +912,7 @@ __global__ void __launch_bounds__(64) k_integrate(const Params<M>* __restrict__ 
                 L.t = S.scal[0 * S.ld + slot];
                 L.h = S.scal[1 * S.ld + slot];
                 L.c_lu = S.scal[2 * S.ld + slot];
+                L.eta = S.scal[3 * S.ld + slot];
                 L.k = S.ints[0 * S.ld + slot];
                 L.neq = S.ints[1 * S.ld + slot];
                 L.att = S.ints[2 * S.ld + slot];
@@ -952,6 +970,7 @@ __global__ void __launch_bounds__(64) k_integrate(const Params<M>* __restrict__ 
                 S.scal[0 * S.ld + slot] = L.t;
                 S.scal[1 * S.ld + slot] = L.h;
                 S.scal[2 * S.ld + slot] = L.c_lu;
+                S.scal[3 * S.ld + slot] = L.eta;
                 S.ints[0 * S.ld + slot] = L.k;
                 S.ints[1 * S.ld + slot] = L.neq;
                 S.ints[2 * S.ld + slot] = L.att;
