@@ -361,6 +361,28 @@ struct Lane {
     unsigned long long n_steps, n_att, n_rhs, n_jac, n_lu, n_solve;
 };
 
+// Weight 1/x of the error norms; the weights only scale tolerances, so the
+// FP32 reciprocal (one instruction, ~1 ulp of FP32) is enough.
+__device__ __forceinline__ double inv_weight(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return (double)__builtin_amdgcn_rcpf((float)x);
+#else
+    return (double)(1.0f / (float)x);
+#endif
+}
+
+// weighted mean square (the square of wrms)
+template <int N>
+__device__ __forceinline__ double wms(const double* v, const double* isc) {
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < N; i++) {
+        const double r = v[i] * isc[i];
+        s += r * r;
+    }
+    return s * (1.0 / N);
+}
+
 template <int N>
 __device__ __forceinline__ double wrms(const double* v, const double* isc) {
     double s = 0.0;
@@ -505,7 +527,7 @@ __device__ __forceinline__ int bdf_attempt(const Params<M>& P, Lane<M>& L, doubl
         }
         yp[i] = a;
         psi[i] = b / gk;
-        isc[i] = 1.0 / (atol + rtol * fabs(a));
+        isc[i] = inv_weight(atol + rtol * fabs(a));
     }
     if (lu_ready) {
         const double tol = fmax(10.0 * EPS / rtol, fmin(0.03, sqrt(rtol)));
@@ -573,12 +595,12 @@ __device__ __forceinline__ int bdf_attempt(const Params<M>& P, Lane<M>& L, doubl
             double e1[N];
 #pragma unroll
             for (int i = 0; i < N; i++) {
-                ise[i] = 1.0 / (atol + rtol * fabs(yn[i]));
+                ise[i] = inv_weight(atol + rtol * fabs(yn[i]));
                 e1[i] = d[i] * (1.0 / (k + 1));
             }
-            en = wrms<N>(e1, ise);
+            en = wms<N>(e1, ise);   // squared: the powers below take half exponents
             if (en > 1.0) {
-                fac = fmax(0.2, 0.9 * ctl_pow(en, -1.0 / (k + 1)));
+                fac = fmax(0.2, 0.9 * ctl_pow(en, -0.5 / (k + 1)));
                 resc = true;
             }
         }
@@ -587,21 +609,19 @@ __device__ __forceinline__ int bdf_attempt(const Params<M>& P, Lane<M>& L, doubl
             L.n_steps++;
             L.t = tn;
             L.jac_fresh = false;
+            // written with selects only: no branches on the order
 #pragma unroll
             for (int i = 0; i < N; i++) {
                 double dk1 = 0.0;   // D_{k+1}
 #pragma unroll
-                for (int j = 1; j <= MAXORD + 1; j++)
-                    if (j == k + 1) dk1 = D[j][i];
+                for (int j = 1; j <= MAXORD + 1; j++) dk1 = (j == k + 1) ? D[j][i] : dk1;
                 double acc = d[i];
 #pragma unroll
                 for (int j = ND - 1; j >= 0; j--) {
-                    if (j == k + 2) D[j][i] = d[i] - dk1;
-                    else if (j == k + 1) D[j][i] = d[i];
-                    else if (j <= k) {
-                        acc = D[j][i] + acc;
-                        D[j][i] = acc;
-                    }
+                    const double upd = D[j][i] + acc;
+                    const double nv = (j == k + 2) ? d[i] - dk1 : ((j == k + 1) ? d[i] : ((j <= k) ? upd : D[j][i]));
+                    acc = (j <= k) ? upd : acc;
+                    D[j][i] = nv;
                 }
             }
             L.neq++;
@@ -620,7 +640,7 @@ __device__ __forceinline__ int bdf_attempt(const Params<M>& P, Lane<M>& L, doubl
                                 if (j == k) a = D[j][i];
                             v[i] = a * (1.0 / k);
                         }
-                        em = wrms<N>(v, ise);
+                        em = wms<N>(v, ise);
                     }
                     if (k < MAXORD) {
 #pragma unroll
@@ -631,12 +651,12 @@ __device__ __forceinline__ int bdf_attempt(const Params<M>& P, Lane<M>& L, doubl
                                 if (j == k + 2) a = D[j][i];
                             v[i] = a * (1.0 / (k + 2));
                         }
-                        ep = wrms<N>(v, ise);
+                        ep = wms<N>(v, ise);
                     }
                 }
-                const double f0 = ctl_pow(en, -1.0 / (k + 1));
-                const double fm = (k > 1) ? ctl_pow(em, -1.0 / k) : 0.0;
-                const double fp = (k < MAXORD) ? ctl_pow(ep, -1.0 / (k + 2)) : 0.0;
+                const double f0 = ctl_pow(en, -0.5 / (k + 1));
+                const double fm = (k > 1) ? ctl_pow(em, -0.5 / k) : 0.0;
+                const double fp = (k < MAXORD) ? ctl_pow(ep, -0.5 / (k + 2)) : 0.0;
                 int dk = 0;
                 double best = f0;
                 if (fm > best) {
@@ -675,7 +695,7 @@ __device__ __forceinline__ void bdf_init(const Params<M>& P, Lane<M>& L, double 
     double d1 = 0.0, h0 = 0.0;
 #pragma unroll
     for (int i = 0; i < N; i++) {
-        isc[i] = 1.0 / (atol + rtol * fabs(y0[i]));
+        isc[i] = inv_weight(atol + rtol * fabs(y0[i]));
         y1[i] = y0[i];
     }
     // f(y0), then f(y0 + h0 f(y0)): one evaluation site for both
