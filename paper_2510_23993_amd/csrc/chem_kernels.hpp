@@ -354,6 +354,7 @@ struct Lane {
     static constexpr int N = M::N;
     double t, tend, h, c_lu, rho;
     double eta;   // Newton contraction estimate theta/(1 - theta) carried between attempts
+    double yin[M::N > M::NN ? M::N - M::NN : 1];   // species in no reaction: constant over the step
     int k, neq, att, round_att;
     bool lu_ok, jac_fresh, last;   // last: the next attempt ends on t_end
     int piv[M::NN];
@@ -371,8 +372,10 @@ __device__ __forceinline__ double inv_weight(double x) {
 #endif
 }
 
-// weighted mean square (the square of wrms)
-template <int N>
+// weighted mean square (the square of wrms) over the first N entries, as a
+// mean over DIV components (the integrated components are the state less
+// its constant inert species, whose entries are zero in every norm)
+template <int N, int DIV = N>
 __device__ __forceinline__ double wms(const double* v, const double* isc) {
     double s = 0.0;
 #pragma unroll
@@ -380,18 +383,28 @@ __device__ __forceinline__ double wms(const double* v, const double* isc) {
         const double r = v[i] * isc[i];
         s += r * r;
     }
-    return s * (1.0 / N);
+    return s * (1.0 / DIV);
 }
 
-template <int N>
+template <int N, int DIV = N>
 __device__ __forceinline__ double wrms(const double* v, const double* isc) {
-    double s = 0.0;
+    return sqrt(wms<N, DIV>(v, isc));
+}
+
+// full state y (N components) from the integrated components yr (the
+// Newton system's order) and the constant inert species
+template <class M>
+__device__ __forceinline__ void expand_state(const double* yr, const double* yin, double* y) {
+    int q = 0;
 #pragma unroll
-    for (int i = 0; i < N; i++) {
-        const double r = v[i] * isc[i];
-        s += r * r;
+    for (int i = 0; i < M::N; i++) {
+        if (M::SYS[i] >= 0) {
+            y[i] = yr[M::SYS[i]];
+        } else {
+            y[i] = yin[q];
+            q++;
+        }
     }
-    return sqrt(s * (1.0 / N));
 }
 
 // D_j <- nabla'^j P(t_n) on the grid of spacing rho*h (j = 1..k; D_0 unchanged):
@@ -469,9 +482,11 @@ __device__ __forceinline__ bool next_step(Lane<M>& L, double& fac, double& hn) {
 // re-samples the same interpolating polynomial.  The last step is flagged
 // there, so the next attempt lands exactly on t_end.
 template <class M>
-__device__ __forceinline__ int bdf_attempt(const Params<M>& P, Lane<M>& L, double (&D)[ND][M::N], double* A,
+__device__ __forceinline__ int bdf_attempt(const Params<M>& P, Lane<M>& L, double (&D)[ND][M::NN], double* A,
                            double rtol, double atol) {
-    constexpr int N = M::N;
+    // the integrated components: the Newton system's (species that react,
+    // then T); norms are means over all N components (inert entries are 0)
+    constexpr int N = M::N, NI = M::NN;
     constexpr double EPS = 2.220446049250313e-16;
     L.att++;
     L.round_att++;
@@ -483,21 +498,22 @@ __device__ __forceinline__ int bdf_attempt(const Params<M>& P, Lane<M>& L, doubl
     int res = SR_RETRY;
     bool resc = false;     // the step size changes by fac for the next attempt
     double fac = 1.0;
-    double ise[N];
+    double ise[NI];
     const double c = L.h / gk;
     bool lu_ready = true;
     if (!L.lu_ok || fabs(c - L.c_lu) > 0.3 * L.c_lu) {
         // the predicted state is formed here and again below, so that no
         // per-component vector stays live across the Jacobian
-        double yj[N];
+        double yr[NI], yj[N];
 #pragma unroll
-        for (int i = 0; i < N; i++) {
+        for (int i = 0; i < NI; i++) {
             double a = 0.0;
 #pragma unroll
             for (int j = 0; j <= MAXORD; j++)
                 if (j <= k) a += D[j][i];
-            yj[i] = a;
+            yr[i] = a;
         }
+        expand_state<M>(yr, L.yin, yj);
         newton_matrix<M>(P, L.rho, yj, c, A);
         L.n_jac++;
         L.n_lu++;
@@ -510,9 +526,9 @@ __device__ __forceinline__ int bdf_attempt(const Params<M>& P, Lane<M>& L, doubl
         }
         lu_ready = L.lu_ok;
     }
-    double yp[N], psi[N], isc[N];
+    double yp[NI], psi[NI], isc[NI];
 #pragma unroll
-    for (int i = 0; i < N; i++) {
+    for (int i = 0; i < NI; i++) {
         double a = 0.0, b = 0.0, gj = 0.0;
 #pragma unroll
         for (int j = 0; j <= MAXORD; j++) {
@@ -531,35 +547,34 @@ __device__ __forceinline__ int bdf_attempt(const Params<M>& P, Lane<M>& L, doubl
     }
     if (lu_ready) {
         const double tol = fmax(10.0 * EPS / rtol, fmin(0.03, sqrt(rtol)));
-        double d[N], yn[N];
+        double d[NI], yn[NI];
 #pragma unroll
-        for (int i = 0; i < N; i++) {
+        for (int i = 0; i < NI; i++) {
             d[i] = 0.0;
             yn[i] = yp[i];
         }
         bool conv = false;
         double dn_old = -1.0;
         for (int it = 0; it < 4; it++) {
-            double f[N];
-            rhs(P, L.rho, yn, f);
+            double f[NI];
+            {
+                double y[N], ff[N];
+                expand_state<M>(yn, L.yin, y);
+                rhs(P, L.rho, y, ff);
+#pragma unroll
+                for (int s = 0; s < NI; s++) f[s] = ff[M::ISYS[s]];
+            }
             L.n_rhs++;
             bool fin = true;
 #pragma unroll
-            for (int i = 0; i < N; i++) {
+            for (int i = 0; i < NI; i++) {
                 f[i] = c * f[i] - psi[i] - d[i];
                 fin = fin && isfinite(f[i]);
             }
             if (!fin) break;
-            {   // solve on the Newton system; inert components keep the residual (identity rows)
-                double fs[M::NN];
-#pragma unroll
-                for (int s = 0; s < M::NN; s++) fs[s] = f[M::ISYS[s]];
-                lu_solve<M::NN, lanes_per_wave<M>()>(A, L.piv, fs);
-#pragma unroll
-                for (int s = 0; s < M::NN; s++) f[M::ISYS[s]] = fs[s];
-            }
+            lu_solve<M::NN, lanes_per_wave<M>()>(A, L.piv, f);
             L.n_solve++;
-            const double dn = wrms<N>(f, isc);
+            const double dn = wrms<NI, N>(f, isc);
             const double rate = dn_old > 0.0 ? dn / dn_old : -1.0;
             if (rate >= 0.0) {
                 double rp = 1.0;
@@ -567,7 +582,7 @@ __device__ __forceinline__ int bdf_attempt(const Params<M>& P, Lane<M>& L, doubl
                 if (rate >= 1.0 || rp / (1.0 - rate) * dn > tol) break;
             }
 #pragma unroll
-            for (int i = 0; i < N; i++) {
+            for (int i = 0; i < NI; i++) {
                 yn[i] += f[i];
                 d[i] += f[i];
             }
@@ -592,13 +607,13 @@ __device__ __forceinline__ int bdf_attempt(const Params<M>& P, Lane<M>& L, doubl
             }
         } else {
             // error test
-            double e1[N];
+            double e1[NI];
 #pragma unroll
-            for (int i = 0; i < N; i++) {
+            for (int i = 0; i < NI; i++) {
                 ise[i] = inv_weight(atol + rtol * fabs(yn[i]));
                 e1[i] = d[i] * (1.0 / (k + 1));
             }
-            en = wms<N>(e1, ise);   // squared: the powers below take half exponents
+            en = wms<NI, N>(e1, ise);   // squared: the powers below take half exponents
             if (en > 1.0) {
                 fac = fmax(0.2, 0.9 * ctl_pow(en, -0.5 / (k + 1)));
                 resc = true;
@@ -611,7 +626,7 @@ __device__ __forceinline__ int bdf_attempt(const Params<M>& P, Lane<M>& L, doubl
             L.jac_fresh = false;
             // written with selects only: no branches on the order
 #pragma unroll
-            for (int i = 0; i < N; i++) {
+            for (int i = 0; i < NI; i++) {
                 double dk1 = 0.0;   // D_{k+1}
 #pragma unroll
                 for (int j = 1; j <= MAXORD + 1; j++) dk1 = (j == k + 1) ? D[j][i] : dk1;
@@ -630,28 +645,28 @@ __device__ __forceinline__ int bdf_attempt(const Params<M>& P, Lane<M>& L, doubl
                 // order and step-size selection
                 double em = 0.0, ep = 0.0;
                 {
-                    double v[N];
+                    double v[NI];
                     if (k > 1) {
 #pragma unroll
-                        for (int i = 0; i < N; i++) {
+                        for (int i = 0; i < NI; i++) {
                             double a = 0.0;
 #pragma unroll
                             for (int j = 2; j <= MAXORD; j++)
                                 if (j == k) a = D[j][i];
                             v[i] = a * (1.0 / k);
                         }
-                        em = wms<N>(v, ise);
+                        em = wms<NI, N>(v, ise);
                     }
                     if (k < MAXORD) {
 #pragma unroll
-                        for (int i = 0; i < N; i++) {
+                        for (int i = 0; i < NI; i++) {
                             double a = 0.0;
 #pragma unroll
                             for (int j = 3; j <= MAXORD + 1; j++)
                                 if (j == k + 2) a = D[j][i];
                             v[i] = a * (1.0 / (k + 2));
                         }
-                        ep = wms<N>(v, ise);
+                        ep = wms<NI, N>(v, ise);
                     }
                 }
                 const double f0 = ctl_pow(en, -0.5 / (k + 1));
@@ -678,54 +693,69 @@ __device__ __forceinline__ int bdf_attempt(const Params<M>& P, Lane<M>& L, doubl
     if (!next_step(L, fac, hn)) return SR_FAIL;
     resc = resc || L.last;
     if (resc) {
-        rescale<N>(D, L.k, fac);
+        rescale<NI>(D, L.k, fac);
         L.h = hn;
         L.neq = 0;
     }
     return res;
 }
 
-// Initial state of a fresh cell: D_0 = y0, D_1 = h f(y0), order 1, with the
-// starting step of Hairer, Norsett & Wanner (Solving ODEs I, Sec. II.4).
+// Initial state of a fresh cell from its full state y0 (N components):
+// D_0 = y0, D_1 = h f(y0) over the integrated components, the inert species
+// kept aside, order 1, with the starting step of Hairer, Norsett & Wanner
+// (Solving ODEs I, Sec. II.4).
 template <class M>
-__device__ __forceinline__ void bdf_init(const Params<M>& P, Lane<M>& L, double (&D)[ND][M::N], const double* y0,
+__device__ __forceinline__ void bdf_init(const Params<M>& P, Lane<M>& L, double (&D)[ND][M::NN], const double* y0,
                          double rtol, double atol) {
-    constexpr int N = M::N;
-    double f0[N], isc[N], y1[N], f1[N];
+    constexpr int N = M::N, NI = M::NN;
+    {
+        int q = 0;
+#pragma unroll
+        for (int i = 0; i < N; i++)
+            if (M::SYS[i] < 0) L.yin[q++] = y0[i];
+    }
+    double r0[NI], f0[NI], isc[NI], y1[N], f1[NI];
     double d1 = 0.0, h0 = 0.0;
 #pragma unroll
-    for (int i = 0; i < N; i++) {
-        isc[i] = inv_weight(atol + rtol * fabs(y0[i]));
-        y1[i] = y0[i];
+    for (int s = 0; s < NI; s++) {
+        r0[s] = y0[M::ISYS[s]];
+        isc[s] = inv_weight(atol + rtol * fabs(r0[s]));
     }
+#pragma unroll
+    for (int i = 0; i < N; i++) y1[i] = y0[i];
     // f(y0), then f(y0 + h0 f(y0)): one evaluation site for both
 #pragma unroll 1
     for (int pass = 0; pass < 2; pass++) {
-        rhs(P, L.rho, y1, f1);
+        {
+            double ff[N];
+            rhs(P, L.rho, y1, ff);
+#pragma unroll
+            for (int s = 0; s < NI; s++) f1[s] = ff[M::ISYS[s]];
+        }
         if (pass == 0) {
 #pragma unroll
-            for (int i = 0; i < N; i++) f0[i] = f1[i];
-            const double d0 = wrms<N>(y0, isc);
-            d1 = wrms<N>(f0, isc);
+            for (int s = 0; s < NI; s++) f0[s] = f1[s];
+            const double d0 = wrms<NI, N>(r0, isc);
+            d1 = wrms<NI, N>(f0, isc);
             h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
             h0 = fmin(h0, L.tend);
 #pragma unroll
-            for (int i = 0; i < N; i++) y1[i] = y0[i] + h0 * f0[i];
+            for (int s = 0; s < NI; s++) y1[M::ISYS[s]] = r0[s] + h0 * f0[s];
         }
     }
     L.n_rhs += 2;
 #pragma unroll
-    for (int i = 0; i < N; i++) f1[i] -= f0[i];
-    const double d2 = wrms<N>(f1, isc) / h0;
+    for (int s = 0; s < NI; s++) f1[s] -= f0[s];
+    const double d2 = wrms<NI, N>(f1, isc) / h0;
     const double mx = fmax(d1, d2);
     const double h1 = (mx <= 1e-15) ? fmax(1e-6, h0 * 1e-3) : sqrt(0.01 / mx);
     L.h = fmin(fmin(100.0 * h0, h1), L.tend);
 #pragma unroll
-    for (int i = 0; i < N; i++) {
-        D[0][i] = y0[i];
-        D[1][i] = L.h * f0[i];
+    for (int s = 0; s < NI; s++) {
+        D[0][s] = r0[s];
+        D[1][s] = L.h * f0[s];
 #pragma unroll
-        for (int j = 2; j < ND; j++) D[j][i] = 0.0;
+        for (int j = 2; j < ND; j++) D[j][s] = 0.0;
     }
     L.t = 0.0;
     L.k = 1;
@@ -740,7 +770,7 @@ __device__ __forceinline__ void bdf_init(const Params<M>& P, Lane<M>& L, double 
 
 // ------------------------------------------------------- integration kernel
 struct SaveArea {             // per active slot, lane-major [field][slot]
-    double* D;                // ND * N rows
+    double* D;                // ND * NN rows (the integrated components)
     double* LU;               // N * N rows
     double* scal;             // 4 rows: t, h, c_lu, eta
     int* ints;                // 4 rows: k, neq, att, flags(lu_ok | jac_fresh<<1 | last<<2)
@@ -859,7 +889,7 @@ __global__ void __launch_bounds__(64) k_integrate(const Params<M>* __restrict__ 
     }
     const int kmax = (MODE == BULK && a.kmax_dev) ? *a.kmax_dev : a.kmax;
     const int64_t n_items = (MODE == PLAIN) ? a.n_items_host : (int64_t)*a.n_items_dev;
-    double D[ND][N];
+    double D[ND][NN];
 
     Lane<M> L;
     L.n_steps = L.n_att = L.n_rhs = L.n_jac = L.n_lu = L.n_solve = 0;
@@ -924,7 +954,7 @@ __global__ void __launch_bounds__(64) k_integrate(const Params<M>* __restrict__ 
             if (MODE != PLAIN && a.flag[slot] == 1) {
                 const SaveArea& S = a.sv;
 #pragma unroll
-                for (int r = 0; r < ND * N; r++) D[r / N][r % N] = S.D[r * S.ld + slot];
+                for (int r = 0; r < ND * NN; r++) D[r / NN][r % NN] = S.D[r * S.ld + slot];
 #pragma unroll 4
                 for (int r = 0; r < NN * NN; r++) A[r * LW] = S.LU[r * S.ld + slot];
 #pragma unroll
@@ -940,6 +970,10 @@ __global__ void __launch_bounds__(64) k_integrate(const Params<M>* __restrict__ 
                 L.lu_ok = fl & 1;
                 L.jac_fresh = (fl >> 1) & 1;
                 L.last = (fl >> 2) & 1;
+                int q = 0;   // inert species: unchanged in Y until the write-back
+#pragma unroll
+                for (int k = 0; k < NS; k++)
+                    if (M::SYS[k] < 0) L.yin[q++] = B.Y[k * B.ldY + i];
             } else {
                 double y0[N];
 #pragma unroll
@@ -971,8 +1005,9 @@ __global__ void __launch_bounds__(64) k_integrate(const Params<M>* __restrict__ 
                 const DevBox& B = a.boxes[bidx];
                 const int64_t i = g - B.off;
 #pragma unroll
-                for (int k = 0; k < NS; k++) B.Y[k * B.ldY + i] = D[0][k];
-                B.T[i] = D[0][NS];
+                for (int k = 0; k < NS; k++)
+                    if (M::SYS[k] >= 0) B.Y[k * B.ldY + i] = D[0][M::SYS[k]];   // inert species unchanged
+                B.T[i] = D[0][M::SYS[NS]];
                 // a cell the surrogate handed over reports that it was integrated instead
                 const uint8_t fin = (st == ST_DONE && a.st_int[g] == ST_SURR_REJ) ? (uint8_t)ST_SURR_REJ : st;
                 a.st_int[g] = fin;
@@ -982,7 +1017,7 @@ __global__ void __launch_bounds__(64) k_integrate(const Params<M>* __restrict__ 
             } else {
                 const SaveArea& S = a.sv;
 #pragma unroll
-                for (int rr = 0; rr < ND * N; rr++) S.D[rr * S.ld + slot] = D[rr / N][rr % N];
+                for (int rr = 0; rr < ND * NN; rr++) S.D[rr * S.ld + slot] = D[rr / NN][rr % NN];
 #pragma unroll 4
                 for (int rr = 0; rr < NN * NN; rr++) S.LU[rr * S.ld + slot] = A[rr * LW];
 #pragma unroll

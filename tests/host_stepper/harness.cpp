@@ -81,7 +81,7 @@ int hs_integrate(const char* mech_path, int pow_mode, int64_t n, const double* r
     g_pow_mode = pow_mode;
     constexpr int N = M::N, NN = M::NN, LW = lanes_per_wave<M>();
     static double A[NN * NN * LW];
-    double D[ND][N];
+    double D[ND][M::NN];
     for (int64_t i = 0; i < n; i++) {
         Lane<M> L{};
         L.rho = rho[i];
@@ -104,8 +104,9 @@ int hs_integrate(const char* mech_path, int pow_mode, int64_t n, const double* r
             }
             if (L.att >= kmax) break;
         }
-        for (int k = 0; k < M::NS; k++) Y[k * n + i] = D[0][k];
-        T[i] = D[0][M::NS];
+        for (int k = 0; k < M::NS; k++)
+            if (M::SYS[k] >= 0) Y[k * n + i] = D[0][M::SYS[k]];
+        T[i] = D[0][M::SYS[M::NS]];
         status[i] = st;
         attempts[i] = L.att;
     }
