@@ -927,8 +927,8 @@ __global__ void k_prepare_coop(CoopMech M, int64_t n, const double* __restrict__
 
 // ------------------------------------------------------------------ kernels
 struct CoopSave {          // per active slot, [field][slot]
-    double* D;             // ND*NC fields
-    double* A;             // NC*NC fields
+    double* D;             // ND*n fields (the n components)
+    double* A;             // n*n fields
     double* scal;          // t, h, c_lu
     int* ints;             // pstep[NC], k, neq, att, flags
     int64_t ld;
@@ -1035,9 +1035,9 @@ __global__ void __launch_bounds__(64, 2) k_integrate_coop(CoopArgs a) {
                 for (int q = 0; q < R; q++) {
                     const int c = l + G * q;
 #pragma unroll
-                    for (int j = 0; j < ND; j++) L.D[j][q] = S.D[(j * NC + c) * S.ld + slot];
+                    for (int j = 0; j < ND; j++) L.D[j][q] = c < n ? S.D[(j * n + c) * S.ld + slot] : 0.0;
                     if (c < n)
-                        for (int col = 0; col < n; col++) jb[col * n + G * q] = S.A[(c * NC + col) * S.ld + slot];
+                        for (int col = 0; col < n; col++) jb[col * n + G * q] = S.A[(c * n + col) * S.ld + slot];
                     L.pstep[q] = S.ints[c * S.ld + slot];
                     if (L.pstep[q] >= 0) gl.perm[L.pstep[q]] = c;
                 }
@@ -1098,10 +1098,11 @@ __global__ void __launch_bounds__(64, 2) k_integrate_coop(CoopArgs a) {
 #pragma unroll
                 for (int q = 0; q < R; q++) {
                     const int c = l + G * q;
+                    if (c < n) {
 #pragma unroll
-                    for (int j = 0; j < ND; j++) S.D[(j * NC + c) * S.ld + slot] = L.D[j][q];
-                    if (c < n)
-                        for (int col = 0; col < n; col++) S.A[(c * NC + col) * S.ld + slot] = jb[col * n + G * q];
+                        for (int j = 0; j < ND; j++) S.D[(j * n + c) * S.ld + slot] = L.D[j][q];
+                        for (int col = 0; col < n; col++) S.A[(c * n + col) * S.ld + slot] = jb[col * n + G * q];
+                    }
                     S.ints[c * S.ld + slot] = L.pstep[q];
                 }
                 if (l == 0) {

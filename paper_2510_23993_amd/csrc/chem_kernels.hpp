@@ -813,29 +813,40 @@ __device__ __forceinline__ int remaining_bin(int att_round, double t0, double t,
     return (int)fmin(ceil(log2(1.0 + rem)), (double)(REM_BINS - 1));
 }
 
-// Per-block counts of the cells a bulk round saved (flag 1) by their
-// completion key, bucket-major: bcnt[key * nb + block].
+// Completion key of an unfinished slot: the key its last round saved
+// (flag 1), or bucket 0 (most work first) for a cell no round has taken yet.
+__device__ __forceinline__ int slot_key(const uint8_t* flag, const uint8_t* key, int64_t slot) {
+    return flag[slot] == 1 ? (key[slot] < REM_BINS ? key[slot] : REM_BINS - 1) : 0;
+}
+
+// Per-block counts of the unfinished cells (flag != 2) by their completion
+// key, bucket-major: bcnt[key * nb + block].  With `ran`, nothing is done
+// unless bulk round r ran (the counts of the last build stay valid).
 __global__ void __launch_bounds__(256) k_key_count(const uint8_t* __restrict__ flag, const uint8_t* __restrict__ key,
-                                                   const int* __restrict__ n_items, int* __restrict__ bcnt, int nb) {
+                                                   const int* __restrict__ n_items, int* __restrict__ bcnt, int nb,
+                                                   const int* __restrict__ ran, int r) {
     __shared__ int hist[REM_BINS];
+    if (ran && *ran <= r) return;
     const int64_t slot = blockIdx.x * 256ll + threadIdx.x;
     if (threadIdx.x < REM_BINS) hist[threadIdx.x] = 0;
     __syncthreads();
-    if (slot < *n_items && flag[slot] == 1) atomicAdd(&hist[key[slot] < REM_BINS ? key[slot] : REM_BINS - 1], 1);
+    if (slot < *n_items && flag[slot] != 2) atomicAdd(&hist[slot_key(flag, key, slot)], 1);
     __syncthreads();
     if (threadIdx.x < REM_BINS) bcnt[threadIdx.x * nb + blockIdx.x] = hist[threadIdx.x];
 }
 
-// items[off[key * nb + block] + rank] = slot for the saved cells, rank = the
-// slot's position among the block's saved slots of that key: a stable
-// counting sort, most remaining work first.
+// items[off[key * nb + block] + rank] = slot for the unfinished cells, rank
+// = the slot's position among the block's unfinished slots of that key: a
+// stable counting sort, most remaining work first.
 __global__ void __launch_bounds__(256) k_key_scatter(const uint8_t* __restrict__ flag, const uint8_t* __restrict__ key,
                                                      const int* __restrict__ n_items, const int* __restrict__ off,
-                                                     int nb, int* __restrict__ items) {
+                                                     int nb, int* __restrict__ items, const int* __restrict__ ran,
+                                                     int r) {
     __shared__ int wc[4][REM_BINS];
+    if (ran && *ran <= r) return;
     const int64_t slot = blockIdx.x * 256ll + threadIdx.x;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int b = (slot < *n_items && flag[slot] == 1) ? (key[slot] < REM_BINS ? key[slot] : REM_BINS - 1) : -1;
+    const int b = (slot < *n_items && flag[slot] != 2) ? slot_key(flag, key, slot) : -1;
     int within = 0;
     for (int bb = 0; bb < REM_BINS; bb++) {
         const unsigned long long m = wave_ballot(b == bb);

@@ -143,7 +143,7 @@ struct chem_ctx_s {
     Buf st_int, active, sparse, flag, bcnt, boff, ints, ctr, save, boxes;
     Buf key, bcnt64, boff64;   // cost-ordered compaction: bucket per slot, bucket-major block counts
     Buf scan_tmp;              // tile totals and offsets of the large scans
-    Buf items2;                // second item list of the ordered bulk rounds
+    Buf items2;                // the two alternating item lists of the ordered bulk rounds
     // flow step: primitives, face fluxes, the Runge-Kutta stage, chemistry inputs, failure count
     Buf fQ, fF, fU1, fchem, fbad;
     hipEvent_t evf[4] = {};
@@ -203,7 +203,7 @@ int ensure_ws(chem_ctx_s* c, int64_t cells, size_t per_slot) {
         c->flag.grow(cells) || c->bcnt.grow(nb * 4) || c->boff.grow(nb * 4) ||
         c->ints.grow(I_COUNT * 4) || c->ctr.grow(2 * sizeof(Counters)) || c->key.grow(cells) ||
         c->bcnt64.grow(nb * 4 * COST_BUCKETS) || c->boff64.grow(nb * 4 * COST_BUCKETS) ||
-        c->scan_tmp.grow(2 * 4 * (nb * COST_BUCKETS / SCAN_TILE + 2)) || c->items2.grow(cells * 4))
+        c->scan_tmp.grow(2 * 4 * (nb * COST_BUCKETS / SCAN_TILE + 2)) || c->items2.grow(2 * cells * 4))
         return fail(CHEM_E_NOMEM, "workspace allocation failed");
     if (c->save.grow(per_slot * (size_t)cells)) return fail(CHEM_E_NOMEM, "save-area allocation failed");
     c->cap_cells = cells;
@@ -217,7 +217,9 @@ int ensure_ws(chem_ctx_s* c, int64_t cells, size_t per_slot) {
 }
 
 size_t onelane_slot_bytes(int N) { return sizeof(double) * (ND * N + N * N + 4) + sizeof(int) * 4 + N; }
-size_t coop_slot_bytes(int NC) { return sizeof(double) * (ND * NC + NC * NC + 3) + sizeof(int) * (NC + 4); }
+// the differences and the Newton matrix of the n components only (not the
+// schedule's NC >= n slots), pivot steps and scalars for all NC
+size_t coop_slot_bytes(int n, int NC) { return sizeof(double) * (ND * n + n * n + 3) + sizeof(int) * (NC + 4); }
 
 SaveArea save_area(chem_ctx_s* c, int N) {
     SaveArea s;
@@ -353,17 +355,21 @@ int pipeline_k(chem_ctx_s* c, int64_t total, int nbox, double rtol, double atol)
     if (adapt) {   // round 0 runs kmax_bulk steps; later rounds take the limit from the last round's predictions
         hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, I + I_KR, (int64_t)1, o.kmax_bulk); LAUNCHED();
     }
-    // with cost ordering, the rounds after the first and the sparse phase take
-    // the cells the last round saved, most predicted remaining work first
-    int* lists[2] = {c->sparse.as<int>(), c->items2.as<int>()};
-    auto ordered_list = [&](int* out) -> int {
+    // with cost ordering, the first ORDERED_ROUNDS rounds after the first and
+    // the sparse phase take the unfinished cells most predicted remaining
+    // work first (later rounds run over the active list in its order); a
+    // list is rebuilt only after a round that ran
+    constexpr int ORDERED_ROUNDS = 8;
+    int* lists[2] = {c->items2.as<int>(), c->items2.as<int>() + std::max<int64_t>(total, 1)};
+    auto ordered_list = [&](int* out, int r) -> int {
+        const int* ran = r >= 0 ? I + I_ROUNDS : nullptr;
         hipLaunchKernelGGL(k_key_count, dim3(nb), dim3(256), 0, s, c->flag.as<uint8_t>(), c->key.as<uint8_t>(),
-                           I + I_NACT, c->bcnt64.as<int>(), (int)nb); LAUNCHED();
+                           I + I_NACT, c->bcnt64.as<int>(), (int)nb, ran, r); LAUNCHED();
         if (int rc2 = scan_counts(s, c->bcnt64.as<int>(), nb * REM_BINS, c->boff64.as<int>(), I + I_NSP,
                                   c->scan_tmp.as<int>()))
             return rc2;
         hipLaunchKernelGGL(k_key_scatter, dim3(nb), dim3(256), 0, s, c->flag.as<uint8_t>(), c->key.as<uint8_t>(),
-                           I + I_NACT, c->boff64.as<int>(), (int)nb, out); LAUNCHED();
+                           I + I_NACT, c->boff64.as<int>(), (int)nb, out, ran, r); LAUNCHED();
         return 0;
     };
     mark(c, 0);
@@ -372,7 +378,7 @@ int pipeline_k(chem_ctx_s* c, int64_t total, int nbox, double rtol, double atol)
         b.n_items_dev = I + I_NACT;
         if (o.order) {
             b.rem_key = c->key.as<uint8_t>();
-            if (r > 0) {
+            if (r > 0 && r <= ORDERED_ROUNDS) {
                 b.items = lists[(r - 1) & 1];
                 b.n_items_dev = I + I_UNF + r - 1;
             }
@@ -388,8 +394,8 @@ int pipeline_k(chem_ctx_s* c, int64_t total, int nbox, double rtol, double atol)
             b.rem_hist = (unsigned*)(I + I_HIST + r * REM_BINS);
         }
         hipLaunchKernelGGL((k_integrate<K, BULK>), dim3(grid), dim3(64), 0, s, PK, b); LAUNCHED();
-        if (o.order) {
-            if (int rc2 = ordered_list(lists[r & 1])) return rc2;
+        if (o.order && r < ORDERED_ROUNDS && r + 1 < rounds) {
+            if (int rc2 = ordered_list(lists[r & 1], r)) return rc2;
         }
         if (adapt && r + 1 < rounds) {
             hipLaunchKernelGGL(k_next_kmax, dim3(1), dim3(64), 0, s, (const unsigned*)(I + I_HIST + r * REM_BINS),
@@ -398,8 +404,8 @@ int pipeline_k(chem_ctx_s* c, int64_t total, int nbox, double rtol, double atol)
     }
     mark(c, 1);
     int* sparse_list = c->sparse.as<int>();
-    if (o.order && rounds > 0) {
-        sparse_list = lists[(rounds - 1) & 1];   // built after the last round (I_NSP holds its length)
+    if (o.order) {
+        if (int rc2 = ordered_list(sparse_list, -1)) return rc2;   // every unfinished cell; I_NSP = its length
     } else {
         hipLaunchKernelGGL(k_count_unfinished, dim3(nb), dim3(256), 0, s, c->flag.as<uint8_t>(), I + I_NACT,
                            c->bcnt.as<int>()); LAUNCHED();
@@ -758,7 +764,7 @@ int prepare_ws(chem_ctx_s* c, int64_t total) {
     }
     const int NC = G * coop_R(G);
     const bool save = c->opt.algorithm == 1 && c->opt.max_rounds > 0;
-    return ensure_ws(c, cells, save ? coop_slot_bytes(NC) : 8);
+    return ensure_ws(c, cells, save ? coop_slot_bytes(c->m->hm.ns + 1, NC) : 8);
 }
 
 // Device workspace of one cooperative pipeline run, as raw pointers (into the
@@ -783,15 +789,15 @@ WsView ctx_view(chem_ctx_s* c) {
                   c->boxes.as<DevBox>(), c->save.as<char>(), c->cap_cells};
 }
 
-CoopSave coop_save_area(const WsView& w, int NC) {
+CoopSave coop_save_area(const WsView& w, int n) {
     CoopSave s;
     const int64_t L = w.cap_cells;
     char* p = w.save;
     s.ld = L;
     s.D = (double*)p;
-    p += sizeof(double) * ND * NC * L;
+    p += sizeof(double) * ND * n * L;
     s.A = (double*)p;
-    p += sizeof(double) * NC * NC * L;
+    p += sizeof(double) * n * n * L;
     s.scal = (double*)p;
     p += sizeof(double) * 3 * L;
     s.ints = (int*)p;
@@ -826,7 +832,7 @@ int pipeline_coop_ws(chem_ctx_s* c, int G, int64_t total, int nbox, double rtol,
     a.st_int = w.st_int;
     a.active_ids = w.active;
     a.flag = w.flag;
-    a.sv = coop_save_area(w, NC);
+    a.sv = coop_save_area(w, c->m->hm.ns + 1);
     a.rtol = rtol;
     a.atol = atol;
     a.ctr = ctr;

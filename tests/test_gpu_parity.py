@@ -155,7 +155,11 @@ def test_bulk_sparse_bitwise_equals_plain(chem, mech, m9, group):
                  # step limits set from the completion predictions
                  {"algorithm": 1, "nactive_star": 500, "kmax_bulk": 3, "order": 1},
                  {"algorithm": 1, "nactive_star": 0, "kmax_bulk": 2, "kmax_adapt": 0.5},
-                 {"algorithm": 1, "nactive_star": 300, "kmax_bulk": 4, "order": 1, "kmax_adapt": 0.75}):
+                 {"algorithm": 1, "nactive_star": 300, "kmax_bulk": 4, "order": 1, "kmax_adapt": 0.75},
+                 # no round runs (N* above the active count): every cell comes from the ordered sparse list
+                 {"algorithm": 1, "nactive_star": 1e9, "order": 1},
+                 # more rounds than the ordered ones: later rounds run over the active list
+                 {"algorithm": 1, "nactive_star": 0, "kmax_bulk": 1, "order": 1}):
         ctx = chem.Context(mech, t_react_min=0.0, group=group, **opts)
         Yg, Tg, st, stats = run_gpu(ctx, rho, e, c.Y, c.T, c.dt, RTOL_C1, ATOL_C1)
         assert np.all(st == 0)
