@@ -713,7 +713,9 @@ def bench_m53(args, torch, chem, fields, oracle):
     1e-10 on this mechanism), 64 lanes per cell, no bulk rounds.  The cells
     may be split into `chunks` consecutive calls (each prints a progress
     line).  The CPU oracle runs on a stratified sample (by temperature
-    decile) and its full-field time is extrapolated."""
+    decile) and its full-field time is extrapolated; a smaller stratified
+    sample (4 cells per decile) is checked against the oracle at rtol 1e-10 /
+    atol 1e-20 for the 1e-4 / 1 K budget."""
     log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
     mech = chem.Mechanism(fields.M53_PATH)
     cells = fields.c4_cells(args.cells, seed=1004)
@@ -722,6 +724,9 @@ def bench_m53(args, torch, chem, fields, oracle):
     ctx0 = chem.Context(mech)
     chunk = (n + args.chunks - 1) // args.chunks
     total_ms, steps, incomplete = 0.0, 0, 0
+    dec = np.minimum((cells.T - 800.0) / 180.0, 9).astype(int)
+    chk = stratified_sample(dec, {k: 4 for k in range(10)}, seed=2004)
+    Ychk, Tchk = np.zeros((mech.ns, chk.size)), np.zeros(chk.size)
     for c0 in range(0, n, chunk):
         c1 = min(n, c0 + chunk)
         sub = fields.Cells(T=cells.T[c0:c1], p=cells.p[c0:c1], Y=np.ascontiguousarray(cells.Y[:, c0:c1]),
@@ -730,6 +735,11 @@ def bench_m53(args, torch, chem, fields, oracle):
         F.reset()
         st = ctx.integrate(F.rho, F.e, F.Y, F.T, F.dt, 1e-7, 1e-20, status=F.status)
         total_ms += st["t_total_ms"]
+        sel = np.where((chk >= c0) & (chk < c1))[0]
+        if sel.size:
+            loc = torch.as_tensor(chk[sel] - c0, device=F.Y.device)
+            Ychk[:, sel] = F.Y[:, loc].cpu().numpy()
+            Tchk[sel] = F.T[loc].cpu().numpy()
         steps += st["steps_total"]
         incomplete += st["n_incomplete"]
         log(json.dumps({"cells": [c0, c1], "ms": st["t_total_ms"], "incomplete": st["n_incomplete"]}))
@@ -741,9 +751,14 @@ def bench_m53(args, torch, chem, fields, oracle):
                                   f"{args.chunks} call(s) of up to {chunk} cells",
                       "rtol": 1e-7, "atol": 1e-20, "schedule": "64 lanes per cell, no bulk rounds"},
            "steps_total": steps, "incomplete": incomplete}
+    orc = oracle.Oracle(fields.M53_PATH)
+    rho_c, e_c = orc.state_from_TPY(cells.T[chk], cells.p[chk], cells.Y[:, chk])
+    Yr, Tr, so = orc.integrate(rho_c, e_c, cells.Y[:, chk], cells.dt, 1e-10, 1e-20, T=cells.T[chk],
+                               nthreads=len(os.sched_getaffinity(0)))
+    rel, dT = rel_errors(Ychk, Tchk, Yr, Tr)
+    out["oracle_check"] = {"cells": int(chk.size), "reference": "oracle at rtol 1e-10 / atol 1e-20",
+                           "max_rel": rel, "max_dT_K": dT, "meets_budget": rel <= BUDGET_REL and dT <= BUDGET_T}
     if not args.no_cpu:
-        orc = oracle.Oracle(fields.M53_PATH)
-        dec = np.minimum((cells.T - 800.0) / 180.0, 9).astype(int)
         idx = stratified_sample(dec, {k: 26 for k in range(10)}, seed=1004)
         rho, e = orc.state_from_TPY(cells.T[idx], cells.p[idx], cells.Y[:, idx])
         threads = len(os.sched_getaffinity(0))
