@@ -345,8 +345,9 @@ int chem_mech_hash(chem_mech_t m, uint64_t* hash);
  * b4[10] (W[out][in]).  X is [batch][12] and out [batch][10], row major.
  * ws is a caller-owned workspace of chem_mlp_workspace_floats(batch) floats;
  * chem_mlp_forward with mode 0 (FP32) leaves there the activations that
- * chem_mlp_backward reads; mode 1 is BF16 matrix-core inference.  Errors:
- * CHEM_E_INVAL for NULL or out-of-range arguments, CHEM_E_HIP. */
+ * chem_mlp_backward reads; mode 1 is BF16 matrix-core inference (X and
+ * params then 16-byte aligned).  Errors: CHEM_E_INVAL for NULL, misaligned or
+ * out-of-range arguments, CHEM_E_HIP. */
 int64_t chem_mlp_nparams(void);
 int64_t chem_mlp_workspace_floats(int64_t batch);
 int chem_mlp_forward(void* stream, int64_t batch, const float* params, const float* X, float* out, float* ws,

@@ -1021,7 +1021,8 @@ int surrogate_pass(chem_ctx_s* c, int64_t total, int nbox, double atol) {
         float* O = c->s_out.as<float>();
         uint8_t* ok = c->s_ok.as<uint8_t>();
         const uint16_t* bf = c->s_bf.as<uint16_t>();
-        const mlp::MlpDev net{c->s_params.as<float>(), bf, bf + mlp::NW2H, bf + mlp::NW2H + mlp::NW3H};
+        const mlp::MlpDev net{c->s_params.as<float>(), bf, bf + mlp::NW2H, bf + mlp::NW2H + mlp::NW3H,
+                              bf + mlp::NW2H + mlp::NW3H + mlp::NW4H};
         const int64_t g1 = std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, (int64_t)c->ncu * 8));
         const int64_t g2 = std::max<int64_t>(1, std::min<int64_t>((total + 63) / 64, (int64_t)c->ncu * 16));
         hipLaunchKernelGGL((k_surr_prep<M>), dim3(g1), dim3(256), 0, s, P, tb, db, nbox, ids, nact, cap, X, ok); LAUNCHED();

@@ -32,6 +32,21 @@ constexpr float INV_SQRT2 = 0.70710678118654752f;
 constexpr float INV_SQRT2PI = 0.39894228040143268f;
 
 __device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * INV_SQRT2)); }
+// GELU for the BF16 inference kernel: erf from Abramowitz & Stegun 7.1.26
+// (rational-times-Gaussian form, |error| <= 1.5e-7, far below the BF16
+// rounding of the activations), with the hardware reciprocal and exp2.  With
+// a = |z| and erf(a/sqrt 2) = 1 - poly(t) exp(-a^2/2), both signs of z give
+// GELU(z) = max(z, 0) - a * (poly(t) / 2) exp(-a^2/2); the 1/2 is folded
+// into the coefficients.
+__device__ __forceinline__ float gelu_fast(float z) {
+    const float a = fabsf(z);
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f * INV_SQRT2, a, 1.0f));
+    const float half_poly =
+        t * (0.127414796f + t * (-0.142248368f + t * (0.7107068705f + t * (-0.7265760135f + t * 0.5307027145f))));
+    const float e = __builtin_amdgcn_exp2f(a * a * (-0.5f * 1.4426950408889634f));
+    return fmaf(-a, half_poly * e, fmaxf(z, 0.0f));
+}
+
 __device__ __forceinline__ float gelu_d(float z) {
     return 0.5f * (1.0f + erff(z * INV_SQRT2)) + z * expf(-0.5f * z * z) * INV_SQRT2PI;
 }
@@ -272,9 +287,11 @@ __global__ void k_standardize(int64_t n, int cols, float* __restrict__ D, const 
 }
 
 // ------------------------------------------------------ BF16 MFMA inference
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
-constexpr int HS = NH + 4;   // LDS row stride (bf16 elements): 130 dwords, spreads rows over banks
+constexpr int KB16 = NH / 16;   // K steps of the 32x32x16 products
+constexpr int IW = 8;           // waves per workgroup, one 32-row tile each
+constexpr int KS = 2;           // K steps per staged block of weight fragments
 
 __device__ __forceinline__ uint16_t f2bf(float f) {   // round to nearest even
     uint32_t u = __float_as_uint(f);
@@ -282,120 +299,216 @@ __device__ __forceinline__ uint16_t f2bf(float f) {   // round to nearest even
     return (uint16_t)(u >> 16);
 }
 
-// Dense weights are stored in MFMA B-fragment order: fragment (kb, nb) holds,
-// for lane l, W[nb*32 + l%32][kb*8 + 4*(l/32) + e], e = 0..3, so each
-// fragment is one coalesced 512-byte load.
+// Dense weights are stored in the operand order of v_mfma_f32_32x32x16_bf16
+// (the A order with the layer's outputs as rows): fragment (kb, nb) holds,
+// for lane l, W[nb*32 + l%32][kb*16 + 8*(l/32) + e], e = 0..7 (16 bytes per
+// lane, 1 KB per fragment).
 __global__ void k_to_bf16_frag(const float* __restrict__ W, int nout, int nblk, uint16_t* __restrict__ F) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;   // element of F
-    const int64_t total = (int64_t)(NH / 8) * nblk * 64 * 4;
+    const int64_t total = (int64_t)KB16 * nblk * 64 * 8;
     if (i >= total) return;
-    const int e = (int)(i & 3), lane = (int)((i >> 2) & 63);
-    const int64_t f = i >> 8;
+    const int e = (int)(i & 7), lane = (int)((i >> 3) & 63);
+    const int64_t f = i >> 9;
     const int nb = (int)(f % nblk), kb = (int)(f / nblk);
-    const int row = nb * 32 + (lane & 31), col = kb * 8 + 4 * (lane >> 5) + e;
+    const int row = nb * 32 + (lane & 31), col = kb * 16 + 8 * (lane >> 5) + e;
     F[i] = row < nout ? f2bf(W[(int64_t)row * NH + col]) : (uint16_t)0;
 }
 
-// One 32-row tile through a 256 -> 32*NB dense layer: A from the LDS tile,
-// B fragments from global memory (L2-resident weights), FP32 accumulators.
-// The fragments of the next k-step are in flight while the current step's
-// products run, which hides most of the L2 latency of a wave.
+// First-layer weights in the same order with one 16-deep K step (the 12
+// inputs, zero-padded): fragment nb, lane l holds W1[nb*32 + l%32][8*(l/32) + e],
+// as a BF16 high part (first NH*16 entries) and the BF16 rounding of the rest.
+__global__ void k_w1_frag(const float* __restrict__ W1, uint16_t* __restrict__ F) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= NW1H / 2) return;
+    const int e = (int)(i & 7), lane = (int)((i >> 3) & 63), nb = (int)(i >> 9);
+    const int row = nb * 32 + (lane & 31), k = 8 * (lane >> 5) + e;
+    const float w = k < NIN ? W1[(int64_t)row * NIN + k] : 0.f;
+    const uint16_t hi = f2bf(w);
+    F[i] = hi;
+    F[NW1H / 2 + i] = f2bf(w - __uint_as_float((uint32_t)hi << 16));
+}
+
+// The products are taken transposed, D = W H^T: with the weights as the A
+// operand, accumulator element q of lane l is output 8*(q/4) + 4*(l/32) + q%4
+// (of the 32-output block) for row l%32 of the wave's tile.  The accumulators
+// start at the bias.
 template <int NB>
-__device__ __forceinline__ void tile_mfma(const uint16_t* __restrict__ Hs, const uint16_t* __restrict__ F, int lane,
-                                          f32x16 (&acc)[NB]) {
-    const int r = lane & 31, kh = 4 * (lane >> 5);
-    const bf16x4* Fv = (const bf16x4*)F;
+__device__ __forceinline__ void acc_bias(f32x16 (&acc)[NB], const float* __restrict__ b, int lane) {
+    const float* bl = b + 4 * (lane >> 5);   // one base, constant offsets (16-byte aligned)
 #pragma unroll
     for (int nb = 0; nb < NB; nb++)
 #pragma unroll
-        for (int q = 0; q < 16; q++) acc[nb][q] = 0.f;
-    bf16x4 bn[NB];
-#pragma unroll
-    for (int nb = 0; nb < NB; nb++) bn[nb] = Fv[nb * 64 + lane];
-    for (int kb = 0; kb < NH / 8; kb++) {
-        const bf16x4 a = *(const bf16x4*)(Hs + r * HS + kb * 8 + kh);
-        bf16x4 bc[NB];
-#pragma unroll
-        for (int nb = 0; nb < NB; nb++) bc[nb] = bn[nb];
-        if (kb + 1 < NH / 8) {
-#pragma unroll
-            for (int nb = 0; nb < NB; nb++) bn[nb] = Fv[((int64_t)(kb + 1) * NB + nb) * 64 + lane];
+        for (int g = 0; g < 4; g++) {
+            const float4 v = *(const float4*)(bl + nb * 32 + 8 * g);
+            acc[nb][4 * g] = v.x, acc[nb][4 * g + 1] = v.y, acc[nb][4 * g + 2] = v.z, acc[nb][4 * g + 3] = v.w;
         }
+}
+
+template <class T> __device__ __forceinline__ T* opaque(T* q) {
+    asm volatile("" : "+s"(q));
+    return q;
+}
+
+// The activations of a wave's 32 rows stay in registers between layers, in
+// the accumulator order: Hr[nb][g] is outputs nb*32 + 8g + 4h .. +3 of row r
+// for lane (r = l%32, h = l/32), four BF16 in two dwords (64 registers).
+typedef uint32_t HReg[NH / 32][4][2];
+
+__device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    bf16x2 v;
+    v[0] = (__bf16)a;
+    v[1] = (__bf16)b;
+    return __builtin_bit_cast(uint32_t, v);
+}
+
+template <int NB>
+__device__ __forceinline__ void gelu_to_regs(const f32x16 (&acc)[NB], HReg& Hr) {
 #pragma unroll
-        for (int nb = 0; nb < NB; nb++) acc[nb] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, bc[nb], acc[nb], 0, 0, 0);
+    for (int nb = 0; nb < NB; nb++)
+#pragma unroll
+        for (int g = 0; g < 4; g++) {
+            Hr[nb][g][0] = pack_bf16(gelu_fast(acc[nb][4 * g]), gelu_fast(acc[nb][4 * g + 1]));
+            Hr[nb][g][1] = pack_bf16(gelu_fast(acc[nb][4 * g + 2]), gelu_fast(acc[nb][4 * g + 3]));
+            __builtin_amdgcn_sched_barrier(0);   // one group at a time: bounded register demand
+        }
+}
+
+// B operand of K step kb (inputs kb*16 + 8h + e of row r for lane (r, h)):
+// with s = kb%2, lane (r, 0) holds inputs 16s + 0..3 (its Hr[kb/2][2s]) and
+// lane (r, 1) inputs 16s + 4..7; the second eight are Hr[kb/2][2s+1] of the
+// two lanes.  One exchange between lanes l and l+32 (lanes 32-63 of the
+// first operand with lanes 0-31 of the second) gives every lane its eight.
+__device__ __forceinline__ bf16x8 b_operand(const HReg& Hr, int kb) {
+    const int nb = kb >> 1, s = kb & 1;
+    const auto x0 = __builtin_amdgcn_permlane32_swap(Hr[nb][2 * s][0], Hr[nb][2 * s + 1][0], false, false);
+    const auto x1 = __builtin_amdgcn_permlane32_swap(Hr[nb][2 * s][1], Hr[nb][2 * s + 1][1], false, false);
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    u32x4 u;
+    u[0] = x0[0];
+    u[1] = x1[0];
+    u[2] = x0[1];
+    u[3] = x1[1];
+    return __builtin_bit_cast(bf16x8, u);
+}
+
+// One 256 -> 32*NB dense layer for the workgroup's IW tiles of 32 rows: the
+// weight fragments staged in LDS once per workgroup, KS K steps at a time
+// (double-buffered: the next stage is loaded from L2 while this one's
+// products run), the activations from registers, FP32 accumulators.
+template <int NB>
+__device__ __forceinline__ void wg_layer(const HReg& Hr, const bf16x8* __restrict__ F, bf16x8 (*Bst)[KS * 8 * 64],
+                                         int tid, f32x16 (&acc)[NB]) {
+    const int lane = tid & 63;
+    constexpr int FS = KS * NB * 64;                       // fragments per stage
+    constexpr int PER = (FS + 64 * IW - 1) / (64 * IW);   // fragments per thread and stage
+    bf16x8 g[PER];
+#pragma unroll
+    for (int u = 0; u < PER; u++) {
+        const int e = tid + 64 * IW * u;
+        if (e < FS) Bst[0][e] = F[e];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int st = 0; st < KB16 / KS; st++) {
+        if (st + 1 < KB16 / KS) {
+#pragma unroll
+            for (int u = 0; u < PER; u++) {
+                const int e = tid + 64 * IW * u;
+                if (e < FS) g[u] = F[(int64_t)(st + 1) * FS + e];
+            }
+        }
+        const bf16x8* Bc = Bst[st & 1];
+#pragma unroll
+        for (int ks = 0; ks < KS; ks++) {
+            const bf16x8 h = b_operand(Hr, st * KS + ks);
+#pragma unroll
+            for (int nb = 0; nb < NB; nb++)
+                acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Bc[(ks * NB + nb) * 64 + lane], h, acc[nb], 0, 0, 0);
+        }
+        if (st + 1 < KB16 / KS) {
+#pragma unroll
+            for (int u = 0; u < PER; u++) {
+                const int e = tid + 64 * IW * u;
+                if (e < FS) Bst[(st + 1) & 1][e] = g[u];
+            }
+        }
+        __syncthreads();
     }
 }
 
-// accumulator element q of lane l is row 8*(q/4) + 4*(l/32) + q%4, column l%32
-__device__ __forceinline__ int acc_row(int lane, int q) { return 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3); }
-
-__global__ void __launch_bounds__(64) k_mlp_infer(MlpDev w, int64_t rows_host, const int* __restrict__ rows_dev,
-                                                  const float* __restrict__ X, float* __restrict__ out) {
-    __shared__ __attribute__((aligned(16))) uint16_t Hs[32 * HS];
-    __shared__ float Xs[32 * NIN];
-    const int lane = threadIdx.x;
+__global__ void __launch_bounds__(64 * IW, 2) k_mlp_infer(MlpDev w, int64_t rows_host, const int* __restrict__ rows_dev,
+                                                          const float* __restrict__ X, float* __restrict__ out) {
+    __shared__ __attribute__((aligned(16))) bf16x8 Bst[2][KS * 8 * 64];
+    const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
     const int64_t rows = rows_dev ? (int64_t)*rows_dev : rows_host;
-    const int64_t ntile = (rows + 31) / 32;
-    const float* p = w.p;
-    // first-layer weights and biases of this lane's outputs, loaded once
-    float w1[4][NIN], b1[4];
-#pragma unroll
-    for (int q = 0; q < 4; q++) {
-        const int j = lane + 64 * q;
-#pragma unroll
-        for (int k = 0; k < NIN; k++) w1[q][k] = p[OW1 + j * NIN + k];
-        b1[q] = p[OB1 + j];
-    }
+    const int64_t ntile = (rows + 32 * IW - 1) / (32 * IW);
     for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
-        const int64_t r0 = tile * 32;
-        for (int e = lane; e < 32 * NIN; e += 64) {
-            const int64_t r = r0 + e / NIN;
-            Xs[e] = r < rows ? X[r * NIN + e % NIN] : 0.f;
-        }
-        __syncthreads();
-        // layer 1 on the FP32 units: lane owns outputs lane + 64 q
+        // the weight and bias pointers made opaque per tile, so that their
+        // loads are not hoisted out of the loop to stay live in registers
+        const float* p = opaque(w.p);
+        const bf16x8* W1f = opaque((const bf16x8*)w.w1h);
+        const int64_t r0 = tile * (32 * IW) + 32 * wv;   // this wave's rows
+        const int64_t row = r0 + (lane & 31);
+        HReg Hr;
+        {   // layer 1 on the matrix cores: inputs and weights as hi + lo BF16 parts
+            // (16 significant bits each), the lo x lo product dropped.  Lane
+            // (row r, half h) reads inputs 8h .. 8h+7 of its row (rows are 48 bytes).
+            const int h = lane >> 5;
+            float x[8];
+            if (row < rows) {
+                const float4* xr = (const float4*)(X + row * NIN + 8 * h);
+                const float4 u = xr[0];
+                x[0] = u.x, x[1] = u.y, x[2] = u.z, x[3] = u.w;
+                if (h == 0) {
+                    const float4 v = xr[1];
+                    x[4] = v.x, x[5] = v.y, x[6] = v.z, x[7] = v.w;
+                } else {
+                    x[4] = x[5] = x[6] = x[7] = 0.f;
+                }
+            } else {
 #pragma unroll
-        for (int q = 0; q < 4; q++) {
-            const int j = lane + 64 * q;
-            for (int r = 0; r < 32; r++) {
-                float z = b1[q];
-#pragma unroll
-                for (int k = 0; k < NIN; k++) z = fmaf(w1[q][k], Xs[r * NIN + k], z);
-                Hs[r * HS + j] = f2bf(gelu(z));
+                for (int e = 0; e < 8; e++) x[e] = 0.f;
             }
-        }
-        __syncthreads();
-        // layers 2 and 3 in place: all reads of the tile finish before the
-        // epilogue overwrites it
-#pragma unroll 1
-        for (int layer = 0; layer < 2; layer++) {
-            const uint16_t* F = layer == 0 ? w.w2h : w.w3h;
-            const float* b = p + (layer == 0 ? OB2 : OB3);
+            bf16x8 xh, xl;
+#pragma unroll
+            for (int e = 0; e < 8; e++) {
+                const __bf16 hb = (__bf16)x[e];
+                xh[e] = hb;
+                xl[e] = (__bf16)(x[e] - (float)hb);
+            }
             f32x16 acc[NH / 32];
-            tile_mfma<NH / 32>(Hs, F, lane, acc);
-            __syncthreads();
+            acc_bias<NH / 32>(acc, p + OB1, lane);
 #pragma unroll
             for (int nb = 0; nb < NH / 32; nb++) {
-                const int j = nb * 32 + (lane & 31);
-                const float bj = b[j];
-#pragma unroll
-                for (int q = 0; q < 16; q++) Hs[acc_row(lane, q) * HS + j] = f2bf(gelu(acc[nb][q] + bj));
+                const bf16x8 wh = W1f[nb * 64 + lane], wl = W1f[(NH / 32 + nb) * 64 + lane];
+                acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wh, xh, acc[nb], 0, 0, 0);
+                acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wh, xl, acc[nb], 0, 0, 0);
+                acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wl, xh, acc[nb], 0, 0, 0);
+                if (nb & 1) __builtin_amdgcn_sched_barrier(0);   // fragments of two blocks in flight
             }
-            __syncthreads();
+            gelu_to_regs<NH / 32>(acc, Hr);
         }
-        // output layer (10 of 32 columns used)
+#pragma unroll 1
+        for (int layer = 0; layer < 2; layer++) {
+            f32x16 acc[NH / 32];
+            acc_bias<NH / 32>(acc, p + (layer == 0 ? OB2 : OB3), lane);
+            wg_layer<NH / 32>(Hr, (const bf16x8*)(layer == 0 ? w.w2h : w.w3h), Bst, tid, acc);
+            gelu_to_regs<NH / 32>(acc, Hr);
+        }
+        // output layer (10 of 32 outputs used): lane (r, h) holds outputs
+        // 4h .. 4h+3 (q < 4) and 8 + 4h .. (q 4..7) of row r
         f32x16 acc[1];
-        tile_mfma<1>(Hs, w.w4h, lane, acc);
-        const int j = lane & 31;
-        if (j < NOUT) {
-            const float bj = p[OB4 + j];
 #pragma unroll
-            for (int q = 0; q < 16; q++) {
-                const int64_t r = r0 + acc_row(lane, q);
-                if (r < rows) out[r * NOUT + j] = acc[0][q] + bj;
+        for (int q = 0; q < 16; q++) acc[0][q] = 0.f;
+        wg_layer<1>(Hr, (const bf16x8*)w.w4h, Bst, tid, acc);
+        if (row < rows) {
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                const int j = 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+                if (j < NOUT) out[row * NOUT + j] = acc[0][q] + p[OB4 + j];
             }
         }
-        __syncthreads();
     }
 }
 
@@ -447,21 +560,22 @@ namespace chem {
 namespace mlp {
 
 int convert_bf16(hipStream_t s, const float* params, uint16_t* bf) {
-    const int64_t n23 = NW2H, n4 = NW4H;
+    const int64_t n23 = NW2H, n4 = NW4H;   // fragment elements of one 256 x 256 layer and of the padded output layer
     hipLaunchKernelGGL(k_to_bf16_frag, dim3((n23 + 255) / 256), dim3(256), 0, s, params + OW2, NH, NH / 32, bf);
     hipLaunchKernelGGL(k_to_bf16_frag, dim3((n23 + 255) / 256), dim3(256), 0, s, params + OW3, NH, NH / 32, bf + NW2H);
     hipLaunchKernelGGL(k_to_bf16_frag, dim3((n4 + 255) / 256), dim3(256), 0, s, params + OW4, NOUT, 1,
                        bf + NW2H + NW3H);
+    hipLaunchKernelGGL(k_w1_frag, dim3((NW1H / 2 + 255) / 256), dim3(256), 0, s, params + OW1, bf + NW2H + NW3H + NW4H);
     MCHK(hipGetLastError());
     return 0;
 }
 
 int launch_infer(hipStream_t s, const MlpDev& w, int64_t rows_host, const int* rows_dev, int64_t max_rows,
                  const float* X, float* out, int ncu) {
-    const int64_t tiles = (max_rows + 31) / 32;
+    const int64_t tiles = (max_rows + 32 * IW - 1) / (32 * IW);
     if (tiles == 0) return 0;
-    const int64_t grid = std::min<int64_t>(tiles, (int64_t)ncu * 8);
-    hipLaunchKernelGGL(k_mlp_infer, dim3(grid), dim3(64), 0, s, w, rows_host, rows_dev, X, out);
+    const int64_t grid = std::min<int64_t>(tiles, (int64_t)ncu * 2);
+    hipLaunchKernelGGL(k_mlp_infer, dim3(grid), dim3(64 * IW), 0, s, w, rows_host, rows_dev, X, out);
     MCHK(hipGetLastError());
     return 0;
 }
@@ -485,9 +599,11 @@ int chem_mlp_forward(void* stream, int64_t batch, const float* params, const flo
     Ws w = carve(ws, batch);
     const int B = (int)batch;
     if (mode == 1) {
+        if (((uintptr_t)X | (uintptr_t)params) & 15)
+            return set_error(CHEM_E_INVAL, "X and params must be 16-byte aligned for the BF16 kernel");
         int rc = convert_bf16(s, params, w.bf);
         if (rc) return rc;
-        MlpDev d{params, w.bf, w.bf + NW2H, w.bf + NW2H + NW3H};
+        MlpDev d{params, w.bf, w.bf + NW2H, w.bf + NW2H + NW3H, w.bf + NW2H + NW3H + NW4H};
         return launch_infer(s, d, batch, nullptr, batch, X, out, num_cu());
     }
     gemm<false, true, EPI_BIAS_GELU>(s, B, NH, NIN, X, NIN, params + OW1, NIN, w.Z[0], NH, params + OB1, nullptr, w.H[0]);

@@ -16,13 +16,16 @@ static_assert(NPARAM == 137482, "parameter count");
 
 // BF16 copies of the dense layers for the MFMA inference kernel (W4 padded
 // to 32 output rows with zeros); element counts
-constexpr int64_t NW2H = NH * NH, NW3H = NH * NH, NW4H = NOUT_PAD * NH, NBF16 = NW2H + NW3H + NW4H;
+// (and the first layer, K = 12 padded to 16, as high and low BF16 parts)
+constexpr int64_t NW2H = NH * NH, NW3H = NH * NH, NW4H = NOUT_PAD * NH, NW1H = 2 * NH * 16,
+                  NBF16 = NW2H + NW3H + NW4H + NW1H;
 
 struct MlpDev {
     const float* p;          // FP32 parameters (W1, biases read from here)
     const uint16_t* w2h;     // BF16 [NH][NH]
     const uint16_t* w3h;     // BF16 [NH][NH]
     const uint16_t* w4h;     // BF16 [NOUT_PAD][NH]
+    const uint16_t* w1h;     // BF16 hi then lo parts of W1, fragments of [NH][16]
 };
 
 // Convert the FP32 dense weights to the BF16 copies (round to nearest even).
