@@ -31,98 +31,149 @@ namespace {
 constexpr float INV_SQRT2 = 0.70710678118654752f;
 constexpr float INV_SQRT2PI = 0.39894228040143268f;
 
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * INV_SQRT2)); }
-// GELU for the BF16 inference kernel: erf from Abramowitz & Stegun 7.1.26
-// (rational-times-Gaussian form, |error| <= 1.5e-7, far below the BF16
-// rounding of the activations), with the hardware reciprocal and exp2.  With
-// a = |z| and erf(a/sqrt 2) = 1 - poly(t) exp(-a^2/2), both signs of z give
-// GELU(z) = max(z, 0) - a * (poly(t) / 2) exp(-a^2/2); the 1/2 is folded
-// into the coefficients.
-__device__ __forceinline__ float gelu_fast(float z) {
-    const float a = fabsf(z);
+// GELU (the network's exact-erf form) and its derivative, branch free.  erf
+// from Abramowitz & Stegun 7.1.26 (rational-times-Gaussian form, |error| <=
+// 1.5e-7: at the FP32 rounding, far below BF16's), with the hardware
+// reciprocal and exp2.  For a = |z|, erf(a/sqrt 2) = 1 - poly(t) exp(-a^2/2),
+// so the normal tail Phi(-a) = (poly(t)/2) exp(-a^2/2) (the 1/2 folded into
+// the coefficients); e returns exp(-a^2/2).
+__device__ __forceinline__ float normal_tail(float a, float& e) {
     const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f * INV_SQRT2, a, 1.0f));
     const float half_poly =
         t * (0.127414796f + t * (-0.142248368f + t * (0.7107068705f + t * (-0.7265760135f + t * 0.5307027145f))));
-    const float e = __builtin_amdgcn_exp2f(a * a * (-0.5f * 1.4426950408889634f));
-    return fmaf(-a, half_poly * e, fmaxf(z, 0.0f));
+    e = __builtin_amdgcn_exp2f(a * a * (-0.5f * 1.4426950408889634f));
+    return half_poly * e;
 }
 
-__device__ __forceinline__ float gelu_d(float z) {
-    return 0.5f * (1.0f + erff(z * INV_SQRT2)) + z * expf(-0.5f * z * z) * INV_SQRT2PI;
+// both signs of z: GELU(z) = z Phi(z) = max(z, 0) - |z| Phi(-|z|)
+__device__ __forceinline__ float gelu_fast(float z) {
+    float e;
+    const float a = fabsf(z);
+    return fmaf(-a, normal_tail(a, e), fmaxf(z, 0.0f));
+}
+
+// GELU'(z) = Phi(z) + z phi(z), phi(z) = exp(-z^2/2) / sqrt(2 pi)
+__device__ __forceinline__ float gelu_d_fast(float z) {
+    float e;
+    const float tail = normal_tail(fabsf(z), e);
+    const float Phi = z >= 0.0f ? 1.0f - tail : tail;
+    return fmaf(z * INV_SQRT2PI, e, Phi);
 }
 
 // ------------------------------------------------------------ FP32 GEMM
 // C[m][n] = sum_k A(m, k) B(k, n) with A(m, k) = TA ? A[k lda + m] : A[m lda + k]
-// and B(k, n) = TB ? B[n ldb + k] : B[k ldb + n]; 64 x 64 tiles, 16-deep K
-// slices staged in LDS, 4 x 4 outputs per thread.  gridDim.z > 1 splits K
-// into chunks of kc and writes partial z to C + z * M * ldc.
+// and B(k, n) = TB ? B[n ldb + k] : B[k ldb + n], on the FP32 matrix cores
+// (v_mfma_f32_32x32x2_f32: FP32 products and sums).  64 x 64 tiles, one
+// 32 x 32 quadrant per wave, 128-deep K slices staged in LDS (the next slice
+// is read from memory into registers while this one's products run: deep
+// slices keep many loads in flight, as these GEMMs are small and latency
+// bound).  gridDim.z > 1 splits K into chunks of kc (a multiple of GK) and
+// writes partial z to C + z * M * ldc.
 enum { EPI_STORE = 0, EPI_BIAS = 1, EPI_BIAS_GELU = 2, EPI_GELU_BACK = 3 };
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+constexpr int GK = 32;   // K slice
+constexpr int GPT = 64 * GK / 256;   // elements of each tile per thread and slice
 
 template <bool TA, bool TB, int EPI>
 __global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, int kc, const float* __restrict__ A, int lda,
                                               const float* __restrict__ B, int ldb, float* __restrict__ C, int ldc,
                                               const float* __restrict__ bias, const float* __restrict__ aux,
                                               float* __restrict__ H) {
-    __shared__ float As[16][64 + 4];
-    __shared__ float Bs[16][64 + 4];
-    const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
+    __shared__ float As[2][GK][64 + 1];
+    __shared__ float Bs[2][GK][64 + 1];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6, wm = wv >> 1, wn = wv & 1;
     const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
     const int kbeg = blockIdx.z * kc, kend = min(K, kbeg + kc);
     C += (int64_t)blockIdx.z * M * ldc;
-    float acc[4][4];
+    // element i of this thread's share of a slice: (m or n, k) of the A and B tiles,
+    // consecutive threads on consecutive addresses
+    auto a_mk = [&](int i, int& am, int& ak) {
+        const int idx = t + 256 * i;
+        am = TA ? (idx & 63) : (idx / GK);
+        ak = TA ? (idx >> 6) : (idx % GK);
+    };
+    auto b_nk = [&](int i, int& bn, int& bk) {
+        const int idx = t + 256 * i;
+        bn = TB ? (idx / GK) : (idx & 63);
+        bk = TB ? (idx % GK) : (idx >> 6);
+    };
+    float ra[GPT], rb[GPT];
+    auto fetch = [&](int k0) {
 #pragma unroll
-    for (int i = 0; i < 4; i++)
-#pragma unroll
-        for (int j = 0; j < 4; j++) acc[i][j] = 0.f;
-    for (int k0 = kbeg; k0 < kend; k0 += 16) {
-#pragma unroll
-        for (int i = 0; i < 4; i++) {
-            const int idx = t + 256 * i;
-            const int am = TA ? (idx & 63) : (idx >> 4), ak = TA ? (idx >> 6) : (idx & 15);
-            const int gm = m0 + am, gk = k0 + ak;
-            float v = 0.f;
-            if (gm < M && gk < kend) v = TA ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk];
-            As[ak][am] = v;
-            const int bn = TB ? (idx >> 4) : (idx & 63), bk = TB ? (idx & 15) : (idx >> 6);
-            const int gn = n0 + bn, gk2 = k0 + bk;
-            float w = 0.f;
-            if (gn < N && gk2 < kend) w = TB ? B[(int64_t)gn * ldb + gk2] : B[(int64_t)gk2 * ldb + gn];
-            Bs[bk][bn] = w;
+        for (int i = 0; i < GPT; i++) {
+            int am, ak, bn, bk;
+            a_mk(i, am, ak);
+            b_nk(i, bn, bk);
+            // every load is issued, from a clamped address (the value is
+            // dropped at the store to LDS), so that no branch separates them
+            // and none is waited for before this slice's products
+            const int cm = min(m0 + am, M - 1), cka = min(k0 + ak, kend - 1);
+            const int cn = min(n0 + bn, N - 1), ckb = min(k0 + bk, kend - 1);
+            ra[i] = TA ? A[(int64_t)cka * lda + cm] : A[(int64_t)cm * lda + cka];
+            rb[i] = TB ? B[(int64_t)cn * ldb + ckb] : B[(int64_t)ckb * ldb + cn];
         }
-        __syncthreads();
+    };
+    auto stash = [&](int buf, int k0) {
 #pragma unroll
-        for (int kk = 0; kk < 16; kk++) {
-            float a[4], b[4];
-#pragma unroll
-            for (int i = 0; i < 4; i++) a[i] = As[kk][ty + 16 * i];
-#pragma unroll
-            for (int j = 0; j < 4; j++) b[j] = Bs[kk][tx + 16 * j];
-#pragma unroll
-            for (int i = 0; i < 4; i++)
-#pragma unroll
-                for (int j = 0; j < 4; j++) acc[i][j] = fmaf(a[i], b[j], acc[i][j]);
+        for (int i = 0; i < GPT; i++) {
+            int am, ak, bn, bk;
+            a_mk(i, am, ak);
+            b_nk(i, bn, bk);
+            As[buf][ak][am] = (m0 + am < M && k0 + ak < kend) ? ra[i] : 0.f;
+            Bs[buf][bk][bn] = (n0 + bn < N && k0 + bk < kend) ? rb[i] : 0.f;
         }
+    };
+    f32x16 acc;
+#pragma unroll
+    for (int q = 0; q < 16; q++) acc[q] = 0.f;
+    if (kbeg < kend) {
+        fetch(kbeg);
+        stash(0, kbeg);
         __syncthreads();
     }
+    int buf = 0;
+    for (int k0 = kbeg; k0 < kend; k0 += GK) {
+        const bool more = k0 + GK < kend;
+        if (more) fetch(k0 + GK);
+        // A operand: lane l holds A(m = l%32, k = kk + l/32) of the quadrant, B likewise
 #pragma unroll
-    for (int i = 0; i < 4; i++)
-#pragma unroll
-        for (int j = 0; j < 4; j++) {
-            const int m = m0 + ty + 16 * i, n = n0 + tx + 16 * j;
-            if (m >= M || n >= N) continue;
-            const int64_t o = (int64_t)m * ldc + n;
-            float v = acc[i][j];
-            if (EPI == EPI_BIAS || EPI == EPI_BIAS_GELU) v += bias[n];
-            if (EPI == EPI_GELU_BACK) v *= gelu_d(aux[o]);
-            C[o] = v;
-            if (EPI == EPI_BIAS_GELU) H[o] = gelu(v);
+        for (int kk = 0; kk < GK; kk += 2) {
+            const float a = As[buf][kk + (lane >> 5)][wm * 32 + (lane & 31)];
+            const float b = Bs[buf][kk + (lane >> 5)][wn * 32 + (lane & 31)];
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
         }
+        if (more) stash(buf ^ 1, k0 + GK);
+        __syncthreads();
+        buf ^= 1;
+    }
+    // accumulator element q of lane l: row 8*(q/4) + 4*(l/32) + q%4, column l%32.
+    // The epilogue's operands are all requested before any is used.
+    const int n = n0 + wn * 32 + (lane & 31);
+    const int mb = m0 + wm * 32 + 4 * (lane >> 5);
+    auto row = [&](int q) { return mb + 8 * (q >> 2) + (q & 3); };
+    const int cn = min(n, N - 1);
+    const float bn = (EPI == EPI_BIAS || EPI == EPI_BIAS_GELU) ? bias[cn] : 0.f;
+    float v[16], hv[16];
+#pragma unroll
+    for (int q = 0; q < 16; q++) {
+        v[q] = acc[q] + bn;
+        if (EPI == EPI_GELU_BACK) v[q] *= gelu_d_fast(aux[(int64_t)min(row(q), M - 1) * ldc + cn]);
+        if (EPI == EPI_BIAS_GELU) hv[q] = gelu_fast(v[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < 16; q++) {
+        const int m = row(q);
+        if (m >= M || n >= N) continue;
+        const int64_t o = (int64_t)m * ldc + n;
+        C[o] = v[q];
+        if (EPI == EPI_BIAS_GELU) H[o] = hv[q];
+    }
 }
 
 template <bool TA, bool TB, int EPI>
 void gemm(hipStream_t s, int M, int N, int K, const float* A, int lda, const float* B, int ldb, float* C, int ldc,
           const float* bias = nullptr, const float* aux = nullptr, float* H = nullptr, int splits = 1) {
-    const int kc = ((K + splits - 1) / splits + 15) / 16 * 16;
+    const int kc = ((K + splits - 1) / splits + GK - 1) / GK * GK;
     hipLaunchKernelGGL((k_gemm<TA, TB, EPI>), dim3((N + 63) / 64, (M + 63) / 64, splits), dim3(256), 0, s, M, N, K,
                        kc, A, lda, B, ldb, C, ldc, bias, aux, H);
 }
@@ -130,27 +181,43 @@ void gemm(hipStream_t s, int M, int N, int K, const float* A, int lda, const flo
 // out[i] = sum_z part[z * n + i], z in order (deterministic split-K reduction)
 __global__ void k_reduce_splits(int S, int64_t n, const float* __restrict__ part, float* __restrict__ out) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        float v = 0.f;
-        for (int z = 0; z < S; z++) v += part[(int64_t)z * n + i];
-        out[i] = v;
+        // four independent sums (z mod 4), combined in a fixed order
+        float v[4] = {0.f, 0.f, 0.f, 0.f};
+        int z = 0;
+        for (; z + 4 <= S; z += 4)
+#pragma unroll
+            for (int u = 0; u < 4; u++) v[u] += part[(int64_t)(z + u) * n + i];
+        for (; z < S; z++) v[0] += part[(int64_t)z * n + i];
+        out[i] = (v[0] + v[1]) + (v[2] + v[3]);
     }
 }
 
-// column sums of D [rows][cols]: partial[chunk][col] over row chunks
-__global__ void k_colsum_part(int64_t rows, int cols, int64_t rpc, const float* __restrict__ D,
-                              float* __restrict__ part) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= cols) return;
+// column sums of D [rows][cols]: partial[chunk][col] over row chunks; four
+// threads per column take every fourth row, combined in a fixed order
+__global__ void __launch_bounds__(256) k_colsum_part(int64_t rows, int cols, int64_t rpc, const float* __restrict__ D,
+                                                     float* __restrict__ part) {
+    __shared__ float sh[4][64];
+    const int cl = threadIdx.x & 63, ph = threadIdx.x >> 6;
+    const int c = blockIdx.x * 64 + cl;
     const int64_t r0 = blockIdx.y * rpc, r1 = min(rows, r0 + rpc);
-    float v = 0.f;
-    for (int64_t r = r0; r < r1; r++) v += D[r * cols + c];
-    part[(int64_t)blockIdx.y * cols + c] = v;
+    float v0 = 0.f, v1 = 0.f;
+    if (c < cols) {
+        int64_t r = r0 + ph;
+        for (; r + 4 < r1; r += 8) {
+            v0 += D[r * cols + c];
+            v1 += D[(r + 4) * cols + c];
+        }
+        if (r < r1) v0 += D[r * cols + c];
+    }
+    sh[ph][cl] = v0 + v1;
+    __syncthreads();
+    if (ph == 0 && c < cols) part[(int64_t)blockIdx.y * cols + c] = (sh[0][cl] + sh[1][cl]) + (sh[2][cl] + sh[3][cl]);
 }
 
 void colsum(hipStream_t s, int64_t rows, int cols, const float* D, float* part, float* out) {
     const int chunks = 64;
     const int64_t rpc = (rows + chunks - 1) / chunks;
-    hipLaunchKernelGGL(k_colsum_part, dim3((cols + 63) / 64, chunks), dim3(64), 0, s, rows, cols, rpc, D, part);
+    hipLaunchKernelGGL(k_colsum_part, dim3((cols + 63) / 64, chunks), dim3(256), 0, s, rows, cols, rpc, D, part);
     hipLaunchKernelGGL(k_reduce_splits, dim3((cols + 255) / 256), dim3(256), 0, s, chunks, (int64_t)cols, part, out);
 }
 
@@ -288,7 +355,6 @@ __global__ void k_standardize(int64_t n, int cols, float* __restrict__ D, const 
 
 // ------------------------------------------------------ BF16 MFMA inference
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x16 __attribute__((ext_vector_type(16)));
 constexpr int KB16 = NH / 16;   // K steps of the 32x32x16 products
 constexpr int IW = 8;           // waves per workgroup, one 32-row tile each
 constexpr int KS = 2;           // K steps per staged block of weight fragments
