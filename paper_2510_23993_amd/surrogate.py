@@ -126,9 +126,26 @@ def generate_pairs(ctx, n_states, seed, rtol=1e-9, atol=1e-20, chunk=1 << 20, ch
     return X, Tg, dropped
 
 
-def train(X, Tg, steps=20000, batch=4096, seed=7, lr0=1e-3, lr1=1e-5, val_frac=0.02, log=print):
+def save_checkpoint(path, p, m, v, step, steps, batch, seed):
+    """Optimiser state after `step` steps (parameters, Adam moments) and the
+    run's schedule, as an .npz of plain arrays."""
+    tmp = path + ".tmp.npz"
+    np.savez(tmp, params=p.cpu().numpy(), m=m.cpu().numpy(), v=v.cpu().numpy(),
+             schedule=np.array([step, steps, batch, seed], dtype=np.int64))
+    os.replace(tmp, path)
+
+
+def train(X, Tg, steps=20000, batch=4096, seed=7, lr0=1e-3, lr1=1e-5, val_frac=0.02, log=print,
+          checkpoint=None, checkpoint_every=0, resume=None, stop_after=None):
     """Standardises the pairs in place, trains with Adam and a cosine
-    learning-rate decay, and returns (params, normalisation, history)."""
+    learning-rate decay, and returns (params, normalisation, history).
+
+    checkpoint: path of an .npz the optimiser state is written to every
+    `checkpoint_every` steps (0: only at the end or at `stop_after`).
+    resume: such a file; training continues after its step with the same
+    schedule (the minibatches are a function of (seed, step), so a resumed
+    run reproduces an uninterrupted one bit for bit, given the same pairs).
+    stop_after: end after this step (the state is checkpointed)."""
     import torch
     import paper_2510_23993_amd as chem
     M = chem.MLP
@@ -156,6 +173,19 @@ def train(X, Tg, steps=20000, batch=4096, seed=7, lr0=1e-3, lr1=1e-5, val_frac=0
     Xtr, Ttr = X[keep].contiguous(), Tg[keep].contiguous()
     p = torch.as_tensor(init_params(seed), device="cuda")
     m, v, g = torch.zeros_like(p), torch.zeros_like(p), torch.zeros_like(p)
+    first = 1
+    if resume is not None:
+        with np.load(resume, allow_pickle=False) as ck:
+            done, c_steps, c_batch, c_seed = (int(x) for x in ck["schedule"])
+            if (c_steps, c_batch, c_seed) != (steps, batch, seed):
+                raise ValueError(f"checkpoint schedule {(c_steps, c_batch, c_seed)} differs from "
+                                 f"{(steps, batch, seed)}")
+            p.copy_(torch.as_tensor(ck["params"]))
+            m.copy_(torch.as_tensor(ck["m"]))
+            v.copy_(torch.as_tensor(ck["v"]))
+        first = done + 1
+        log(f"resumed after step {done}")
+    last = steps if stop_after is None else min(steps, stop_after)
     Xb = torch.empty((batch, NIN), dtype=torch.float32, device="cuda")
     Tb = torch.empty((batch, NOUT), dtype=torch.float32, device="cuda")
     out = torch.empty((batch, NOUT), dtype=torch.float32, device="cuda")
@@ -174,18 +204,20 @@ def train(X, Tg, steps=20000, batch=4096, seed=7, lr0=1e-3, lr1=1e-5, val_frac=0
 
     hist = []
     t0 = time.perf_counter()
-    for step in range(1, steps + 1):
+    for step in range(first, last + 1):
         lr = lr1 + 0.5 * (lr0 - lr1) * (1.0 + math.cos(math.pi * (step - 1) / steps))
         M.gather(Xtr, Ttr, batch, seed, step, Xb, Tb)
         M.forward(p, Xb, out, ws, mode=0)
         M.mse(out, Tb, dout, loss)
         M.backward(p, Xb, ws, dout, g)
         M.adam(p, g, m, v, step, lr)
-        if step == 1 or step % 2000 == 0 or step == steps:
+        if step == 1 or step % 2000 == 0 or step == last:
             tl = float(loss.item())
             hist.append({"step": step, "train_loss": tl, "lr": lr, "s": time.perf_counter() - t0})
             log(f"step {step}: train loss {tl:.3e}, lr {lr:.2e}, {time.perf_counter() - t0:.1f} s")
-    hist.append({"step": steps, "val_loss": val_loss()})
+        if checkpoint and (step == last or (checkpoint_every and step % checkpoint_every == 0)):
+            save_checkpoint(checkpoint, p, m, v, step, steps, batch, seed)
+    hist.append({"step": last, "val_loss": val_loss()})
     log(f"validation loss {hist[-1]['val_loss']:.3e}")
     span = hi - lo
     norm = {"mean_x": mean_x.cpu().numpy(), "sd_x": sd_x.cpu().numpy(), "mean_t": mean_t.cpu().numpy(),
@@ -247,6 +279,9 @@ def main(argv=None):
     t.add_argument("--batch", type=int, default=4096)
     t.add_argument("--seed", type=int, default=1005)
     t.add_argument("--report", default=None)
+    t.add_argument("--checkpoint", default=None, help="optimiser-state file (.npz), written at the end")
+    t.add_argument("--checkpoint-every", type=int, default=0, help="also every this many steps")
+    t.add_argument("--resume", default=None, help="continue from this optimiser-state file")
     ev = sub.add_parser("evaluate")
     ev.add_argument("--weights", default=DEFAULT_WEIGHTS)
     ev.add_argument("--nz", type=int, default=128)
@@ -265,7 +300,9 @@ def main(argv=None):
         X, Tg, dropped = generate_pairs(ctx, a.pairs // 2, a.seed, log=log)
         t_gen = time.perf_counter() - t0
         log(f"{X.shape[0]} pairs ({dropped} dropped) in {t_gen:.1f} s")
-        params, norm, hist = train(X, Tg, steps=a.steps, batch=a.batch, seed=a.seed, log=log)
+        params, norm, hist = train(X, Tg, steps=a.steps, batch=a.batch, seed=a.seed, log=log,
+                                   checkpoint=a.checkpoint, checkpoint_every=a.checkpoint_every,
+                                   resume=a.resume)
         write_weights(a.out, params, norm["mean_x"], norm["sd_x"], norm["mean_t"], norm["sd_t"],
                       norm["env_lo"], norm["env_hi"], mech.hash)
         log(f"wrote {a.out}")

@@ -67,6 +67,18 @@ double harness_ctl_pow(double x, double y) {
 using namespace chem;
 using M = Mech_m9;
 
+template <int N>
+static int lu_n(const double* A, double* b) {
+    double a[N * N], x[N];
+    int piv[N];
+    for (int i = 0; i < N * N; i++) a[i] = A[i];
+    if (!lu_factor<N, 1>(a, piv)) return 0;
+    for (int i = 0; i < N; i++) x[i] = b[i];
+    lu_solve<N, 1>(a, piv, x);
+    for (int i = 0; i < N; i++) b[i] = x[i];
+    return 1;
+}
+
 extern "C" {
 
 // Integrates n cells (Y[ns][n] column-major and T[n] in/out) over dt with the
@@ -124,6 +136,23 @@ int hs_next_step(double t, double h, double tend, double fac, double* hn, double
     if (!next_step(L, fac, *hn)) return -1;
     *fac_out = fac;
     return L.last ? 1 : 0;
+}
+
+// The library's dense LU (partial pivoting, reciprocal diagonal) and solve
+// on an n x n row-major matrix: b is overwritten by the solution.  Returns 1,
+// 0 if the factorisation reports a zero or non-finite pivot, -1 for an n
+// with no instantiation here.
+int hs_lu(int n, const double* A, double* b) {
+    switch (n) {
+        case 1: return lu_n<1>(A, b);
+        case 2: return lu_n<2>(A, b);
+        case 3: return lu_n<3>(A, b);
+        case 5: return lu_n<5>(A, b);
+        case 9: return lu_n<9>(A, b);
+        case 10: return lu_n<10>(A, b);
+        case 16: return lu_n<16>(A, b);
+        default: return -1;
+    }
 }
 
 }  // extern "C"

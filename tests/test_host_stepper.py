@@ -100,3 +100,34 @@ def test_amr_cells_finish_with_the_bare_instruction_power(hs, m9):
             assert np.all(st == 0), (i, mode, np.bincount(st))
         total += int(act.sum())
     assert total > 20000
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 9, 10, 16])
+def test_library_lu_against_numpy(hs, n):
+    # the one-lane kernel's dense LU and solve (compiled for the CPU) against
+    # numpy's LAPACK solve: random systems, systems that need row exchanges
+    # (zero leading diagonal), and singular or non-finite ones reported
+    rng = np.random.default_rng(7 + n)
+    hs.hs_lu.argtypes = [ctypes.c_int, P, P]
+    for trial in range(40):
+        A = rng.normal(size=(n, n))
+        if trial % 4 == 1 and n > 1:   # a permuted diagonal-heavy matrix: every pivot needs an exchange
+            A = np.roll(np.eye(n) * 3.0 + 0.1 * rng.normal(size=(n, n)), 1, axis=0)
+        if trial % 4 == 2:             # Newton-like matrices I - c J
+            A = np.eye(n) - rng.uniform(1e-3, 1e3) * rng.normal(size=(n, n))
+        b = rng.normal(size=n)
+        x = b.copy()
+        Ac = np.ascontiguousarray(A)
+        assert hs.hs_lu(n, Ac.ctypes.data_as(P), x.ctypes.data_as(P)) == 1
+        ref = np.linalg.solve(A, b)
+        tol = 1e-13 * np.linalg.cond(A) * max(1.0, np.max(np.abs(ref)))
+        assert np.max(np.abs(x - ref)) <= tol, (n, trial)
+    if n > 1:
+        A = rng.normal(size=(n, n))
+        A[:, n // 2] = 0.0             # exactly singular: a zero pivot
+        x = rng.normal(size=n)
+        assert hs.hs_lu(n, np.ascontiguousarray(A).ctypes.data_as(P), x.ctypes.data_as(P)) == 0
+    A = rng.normal(size=(n, n))
+    A[n - 1, n - 1] = np.nan
+    x = rng.normal(size=n)
+    assert hs.hs_lu(n, np.ascontiguousarray(A).ctypes.data_as(P), x.ctypes.data_as(P)) == 0
