@@ -157,6 +157,10 @@ void chem_ctx_destroy(chem_ctx_t c);
  *   group         lanes per cell: 0 = compiled one-lane kernel (if the mechanism's
  *                 structure was compiled in), 4/8/16/32/64 = cooperative kernels,
  *                 -1 = automatic (default)
+ *   cells_per_wave the same choice counted in cells per 64-lane wave: 64 = one
+ *                 lane per cell (group 0; the one-lane kernel's workgroups hold
+ *                 63 or 64 cells, by the mechanism's LDS need), 16/8/4/2/1 =
+ *                 group 4/8/16/32/64, 0 = automatic
  *   use_graph     1 = capture the enqueued pipeline of chem_integrate_boxes in a
  *                 hipGraph and replay it while the box table is unchanged, default 1
  *   surrogate     1 = run the learned surrogate on the active cells before the
@@ -368,6 +372,12 @@ int chem_mlp_gather(void* stream, int64_t n_data, const float* X, const float* T
                     int64_t step, float* Xb, float* Tb);
 /* Column mean and standard deviation of data [n][cols] (cols <= 64); acc is
  * a device scratch of 2 cols doubles. */
+/* Rows idx[0..n) of X [*][12] and T [*][10] copied to rows 0..n) of Xo and To
+ * (device buffers; idx is int64 on the device, every entry a valid row: the
+ * kernel does not check).  The training driver's data split and the
+ * compaction of integrated pairs use it.  CHEM_E_INVAL for NULL pointers or
+ * n < 0. */
+int chem_mlp_take(void* stream, int64_t n, const int64_t* idx, const float* X, const float* T, float* Xo, float* To);
 int chem_mlp_colstats(void* stream, int64_t n, int cols, const float* data, double* acc, float* mean, float* sd);
 /* Column minimum and maximum of data [n][cols] (cols <= 64) into lo, hi
  * (device doubles); scratch is 2 cols unsigned ints of device memory. */

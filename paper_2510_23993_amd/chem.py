@@ -54,8 +54,8 @@ EXPORTS = ["chem_load_mechanism", "chem_mech_info", "chem_species_name", "chem_f
            "chem_load_surrogate", "chem_integrate", "chem_integrate_boxes", "chem_prepare_state",
            "chem_eval_rhs", "chem_synchronize", "chem_last_error", "chem_autotune",
            "chem_mlp_nparams", "chem_mlp_workspace_floats", "chem_mlp_forward", "chem_mlp_backward",
-           "chem_mlp_mse", "chem_mlp_adam", "chem_mlp_gather", "chem_mlp_colstats", "chem_mlp_standardize",
-           "chem_mlp_colrange", "chem_surrogate_pairs", "chem_mech_hash",
+           "chem_mlp_mse", "chem_mlp_adam", "chem_mlp_gather", "chem_mlp_take", "chem_mlp_colstats",
+           "chem_mlp_standardize", "chem_mlp_colrange", "chem_surrogate_pairs", "chem_mech_hash",
            "chem_flow_step", "chem_strang_step", "chem_integrate_noalloc",
            "chem_eval_contractions"]
 
@@ -106,6 +106,7 @@ def lib():
     L.chem_mlp_mse.argtypes = [vp, i64, vp, vp, vp, vp]
     L.chem_mlp_adam.argtypes = [vp, i64, vp, vp, vp, vp, dbl, dbl, dbl, dbl, C.c_int]
     L.chem_mlp_gather.argtypes = [vp, i64, vp, vp, i64, C.c_uint64, i64, vp, vp]
+    L.chem_mlp_take.argtypes = [vp, i64, vp, vp, vp, vp, vp]
     L.chem_mlp_colstats.argtypes = [vp, i64, C.c_int, vp, vp, vp, vp]
     L.chem_mlp_standardize.argtypes = [vp, i64, C.c_int, vp, vp, vp]
     L.chem_mlp_colrange.argtypes = [vp, i64, C.c_int, vp, vp, vp, vp]
@@ -365,6 +366,14 @@ class MLP:
     def gather(X, T, batch, seed, step, Xb, Tb, stream=None):
         _check(lib().chem_mlp_gather(_stream_handle(stream), X.shape[0], _ptr(X), _ptr(T), int(batch),
                                      int(seed) & 0xFFFFFFFFFFFFFFFF, int(step), _ptr(Xb), _ptr(Tb)))
+
+    @staticmethod
+    def take(idx, X, T, Xo, To, stream=None):
+        """Rows idx (int64 device tensor) of X and T into Xo and To."""
+        if idx.element_size() != 8 or idx.is_floating_point():
+            raise TypeError("idx must be int64")
+        _check(lib().chem_mlp_take(_stream_handle(stream), idx.numel(), _ptr(idx), _ptr(X), _ptr(T), _ptr(Xo),
+                                   _ptr(To)))
 
     @staticmethod
     def colstats(data, acc, mean, sd, stream=None):

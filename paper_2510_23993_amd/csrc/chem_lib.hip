@@ -1379,6 +1379,10 @@ int chem_set_option(chem_ctx_t c, const char* key, double v) {
     else if (k == "group" && (v == -1 || v == 0 || v == 4 || v == 8 || v == 16 || v == 32 || v == 64)) {
         if (v == 0 && !c->m->ops) return fail(CHEM_E_INVAL, "no compiled one-lane kernel for this mechanism");
         o.group = (int)v;
+    } else if (k == "cells_per_wave" && (v == 0 || v == 1 || v == 2 || v == 4 || v == 8 || v == 16 || v == 64)) {
+        // the same choice as group, counted in cells per 64-lane wave
+        if (v == 64 && !c->m->ops) return fail(CHEM_E_INVAL, "no compiled one-lane kernel for this mechanism");
+        o.group = v == 0 ? -1 : (v == 64 ? 0 : 64 / (int)v);
     } else return fail(CHEM_E_INVAL, "unknown option or value out of range: " + k);
     return CHEM_OK;
 }
@@ -1397,6 +1401,7 @@ int chem_get_option(chem_ctx_t c, const char* key, double* v) {
     else if (k == "precision") *v = o.precision;
     else if (k == "use_graph") *v = o.use_graph;
     else if (k == "group") *v = o.group;
+    else if (k == "cells_per_wave") *v = o.group < 0 ? 0 : (o.group == 0 ? 64 : 64 / o.group);
     else if (k == "surrogate") *v = o.surrogate;
     else if (k == "surr_rtol") *v = o.surr_rtol;
     else if (k == "round_decay") *v = o.round_decay;

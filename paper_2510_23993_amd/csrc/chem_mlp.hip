@@ -276,6 +276,18 @@ __global__ void k_gather(int64_t n_data, const float* __restrict__ X, const floa
     for (int k = 0; k < NOUT; k++) Tb[i * NOUT + k] = T[r * NOUT + k];
 }
 
+// rows idx[i] of X [*][NIN] and T [*][NOUT] to row i of Xo and To
+__global__ void k_take(int64_t n, const int64_t* __restrict__ idx, const float* __restrict__ X,
+                       const float* __restrict__ T, float* __restrict__ Xo, float* __restrict__ To) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t r = idx[i];
+#pragma unroll
+    for (int k = 0; k < NIN; k++) Xo[i * NIN + k] = X[r * NIN + k];
+#pragma unroll
+    for (int k = 0; k < NOUT; k++) To[i * NOUT + k] = T[r * NOUT + k];
+}
+
 __global__ void k_colstats(int64_t n, int cols, const float* __restrict__ D, double* __restrict__ acc) {
     // acc[2c] += sum x, acc[2c+1] += sum x^2 over this thread's rows
     const int c = threadIdx.x % cols;
@@ -738,6 +750,15 @@ int chem_mlp_gather(void* stream, int64_t n_data, const float* X, const float* T
     if (n_data <= 0 || batch <= 0 || !X || !T || !Xb || !Tb) return set_error(CHEM_E_INVAL, "bad argument");
     hipLaunchKernelGGL(k_gather, dim3((batch + 255) / 256), dim3(256), 0, (hipStream_t)stream, n_data, X, T, batch,
                        seed, step, Xb, Tb);
+    MCHK(hipGetLastError());
+    return 0;
+}
+
+int chem_mlp_take(void* stream, int64_t n, const int64_t* idx, const float* X, const float* T, float* Xo, float* To) {
+    if (n < 0 || (n > 0 && (!idx || !X || !T || !Xo || !To))) return set_error(CHEM_E_INVAL, "bad argument");
+    if (n == 0) return 0;
+    hipLaunchKernelGGL(k_take, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, n, idx, X, T, Xo,
+                       To);
     MCHK(hipGetLastError());
     return 0;
 }

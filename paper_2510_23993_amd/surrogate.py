@@ -89,7 +89,11 @@ def generate_pairs(ctx, n_states, seed, rtol=1e-9, atol=1e-20, chunk=1 << 20, ch
     import torch
     import paper_2510_23993_amd as chem
     from synth import fields
-    Xs, Ts = [], []
+    # the pairs go straight into one buffer; cells the integrator did not
+    # finish are dropped by a row gather (the library's take kernel)
+    Xall = torch.empty((n_states * chain, NIN), dtype=torch.float32, device="cuda")
+    Tall = torch.empty((n_states * chain, NOUT), dtype=torch.float32, device="cuda")
+    off = 0
     dropped = 0
     t0 = time.perf_counter()
     for ci, start in enumerate(range(0, n_states, chunk)):
@@ -111,19 +115,20 @@ def generate_pairs(ctx, n_states, seed, rtol=1e-9, atol=1e-20, chunk=1 << 20, ch
             for _ in range(chain):
                 Y1, T1 = Y.clone(), T.clone()
                 ctx.integrate(rho, e, Y1, T1, dt, rtol, atol, status=status)
-                X = torch.empty((m, NIN), dtype=torch.float32, device="cuda")
-                Tg = torch.empty((m, NOUT), dtype=torch.float32, device="cuda")
+                X, Tg = Xall[off:off + m], Tall[off:off + m]
                 ctx.surrogate_pairs(rho, Y, T, Y1, T1, dtv, X, Tg)
-                ok = status == chem.ST_DONE
-                nok = int(ok.sum().item())
-                dropped += m - nok
-                Xs.append(X[ok] if nok < m else X)
-                Ts.append(Tg[ok] if nok < m else Tg)
+                ok = np.flatnonzero(status.cpu().numpy() == chem.ST_DONE)
+                if ok.size < m:
+                    Xk = torch.empty((ok.size, NIN), dtype=torch.float32, device="cuda")
+                    Tk = torch.empty((ok.size, NOUT), dtype=torch.float32, device="cuda")
+                    chem.MLP.take(torch.as_tensor(ok, dtype=torch.int64, device="cuda"), X, Tg, Xk, Tk)
+                    Xall[off:off + ok.size].copy_(Xk)
+                    Tall[off:off + ok.size].copy_(Tk)
+                dropped += m - ok.size
+                off += ok.size
                 Y, T = Y1, T1
-        log(f"pairs: chunk {ci} done, {sum(x.shape[0] for x in Xs)} pairs, {time.perf_counter() - t0:.1f} s")
-    X = torch.cat(Xs)
-    Tg = torch.cat(Ts)
-    return X, Tg, dropped
+        log(f"pairs: chunk {ci} done, {off} pairs, {time.perf_counter() - t0:.1f} s")
+    return Xall[:off], Tall[:off], dropped
 
 
 def save_checkpoint(path, p, m, v, step, steps, batch, seed):
@@ -162,15 +167,18 @@ def train(X, Tg, steps=20000, batch=4096, seed=7, lr0=1e-3, lr1=1e-5, val_frac=0
     M.standardize(Tg, mean_t, sd_t)
     n_val = max(batch, int(val_frac * N))
     n_tr = N - n_val
-    # held-out rows: a seeded permutation (the pairs arrive grouped by dt)
-    gen = torch.Generator(device="cuda")
-    gen.manual_seed(seed)
-    perm = torch.randperm(N, device="cuda", generator=gen)
-    va = perm[n_tr:]
-    Xva, Tva = X[va].contiguous(), Tg[va].contiguous()
-    keep = torch.ones(N, dtype=torch.bool, device="cuda")
-    keep[va] = False
-    Xtr, Ttr = X[keep].contiguous(), Tg[keep].contiguous()
+    # held-out rows: a seeded permutation (the pairs arrive grouped by dt);
+    # the training rows keep their order.  Rows are gathered by the
+    # library's take kernel.
+    perm = np.random.default_rng(seed).permutation(N)
+    va = torch.as_tensor(perm[n_tr:], dtype=torch.int64, device="cuda")
+    tr = torch.as_tensor(np.sort(perm[:n_tr]), dtype=torch.int64, device="cuda")
+    Xva = torch.empty((n_val, NIN), dtype=torch.float32, device="cuda")
+    Tva = torch.empty((n_val, NOUT), dtype=torch.float32, device="cuda")
+    Xtr = torch.empty((n_tr, NIN), dtype=torch.float32, device="cuda")
+    Ttr = torch.empty((n_tr, NOUT), dtype=torch.float32, device="cuda")
+    M.take(va, X, Tg, Xva, Tva)
+    M.take(tr, X, Tg, Xtr, Ttr)
     p = torch.as_tensor(init_params(seed), device="cuda")
     m, v, g = torch.zeros_like(p), torch.zeros_like(p), torch.zeros_like(p)
     first = 1

@@ -177,3 +177,18 @@ def test_short_training_reduces_loss(chem):
             hist.append(float(loss.item()))
     print(f"training loss {hist[0]:.4f} -> {hist[1]:.4f}")
     assert hist[1] < 0.1 * hist[0]
+
+
+def test_take_rows(chem):
+    import torch
+    rng = np.random.default_rng(46)
+    X = rng.normal(size=(1000, 12))
+    T = rng.normal(size=(1000, 10))
+    idx = rng.integers(0, 1000, 777)
+    Xo = torch.zeros((777, 12), dtype=torch.float32, device="cuda")
+    To = torch.zeros((777, 10), dtype=torch.float32, device="cuda")
+    chem.MLP.take(torch.as_tensor(idx, dtype=torch.int64, device="cuda"), dev(X), dev(T), Xo, To)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(Xo), X[idx].astype(np.float32)) and np.array_equal(host(To), T[idx].astype(np.float32))
+    with pytest.raises(TypeError):
+        chem.MLP.take(torch.zeros(3, dtype=torch.int32, device="cuda"), dev(X), dev(T), Xo, To)

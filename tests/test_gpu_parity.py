@@ -234,3 +234,24 @@ def test_round_decay_gate_stops_rounds_early(chem, mech, m9):
     print(f"bulk rounds: {out[0][0]} without the decay gate, {out[1][0]} with it")
     assert out[1][0] < out[0][0]
     assert np.array_equal(out[0][1], out[1][1]) and np.array_equal(out[0][2], out[1][2])
+
+
+def test_cells_per_wave_selects_the_schedule(chem, mech, m9):
+    # cells_per_wave is group counted per 64-lane wave: setting one reads back
+    # as the other, and the integration equals the same group's bit for bit
+    ctx = chem.Context(mech)
+    for cpw, grp in ((64, 0), (16, 4), (8, 8), (4, 16), (2, 32), (1, 64), (0, -1)):
+        ctx.set_option("cells_per_wave", cpw)
+        assert ctx.get_option("group") == grp and ctx.get_option("cells_per_wave") == cpw
+    for bad in (3, 32, 65, -1):
+        with pytest.raises(chem.ChemError):
+            ctx.set_option("cells_per_wave", bad)
+    c = fields.c1_cells(200, seed=1007)
+    rho, e = oracle_inputs(m9, c)
+    outs = []
+    for key, val in (("cells_per_wave", 8), ("group", 8), ("cells_per_wave", 64), ("group", 0)):
+        cx = chem.Context(mech)
+        cx.set_option(key, val)
+        outs.append(run_gpu(cx, rho, e, c.Y, c.T, c.dt, RTOL_C1, ATOL_C1))
+    for a, b in ((0, 1), (2, 3)):
+        assert np.array_equal(outs[a][0], outs[b][0]) and np.array_equal(outs[a][1], outs[b][1])
