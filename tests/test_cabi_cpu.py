@@ -56,6 +56,9 @@ def test_null_arguments():
     assert L.chem_load_mechanism(None, None) == -1
     assert L.chem_integrate(None, 0, None, None, None, 0, None, None, None, 1.0, 1.0, 1.0, None) == -1
     assert L.chem_integrate_noalloc(None, 0, None, None, None, 0, None, None, None, 1.0, 1.0, 1.0) == -1
+    assert L.chem_mlp_take(None, -1, None, None, None, None, None) == -1
+    assert L.chem_mlp_take(None, 5, None, None, None, None, None) == -1
+    assert L.chem_mlp_take(None, 0, None, None, None, None, None) == 0   # nothing to gather
     assert L.chem_synchronize(None) == -1
     assert b"NULL" in L.chem_last_error()
 
