@@ -1,8 +1,9 @@
 // Surrogate network kernels behind the chem_mlp_* entry points of chem.h:
-// training in FP32 (tiled GEMMs through LDS, fused bias + GELU epilogues,
-// split-K weight gradients reduced in a fixed order, MSE, Adam, counter-based
-// minibatch sampling, feature standardisation) and inference with BF16 MFMA
-// (v_mfma_f32_32x32x8bf16_1k) accumulating in FP32.
+// training in FP32 (GEMMs on the FP32 matrix cores, v_mfma_f32_32x32x2_f32,
+// with tiles staged through LDS and fused bias + GELU epilogues, split-K
+// weight gradients reduced in a fixed order, MSE, Adam, counter-based
+// minibatch sampling, row gathers, feature standardisation) and inference on
+// the BF16 matrix cores (v_mfma_f32_32x32x16_bf16) accumulating in FP32.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
