@@ -180,11 +180,12 @@ def _pmc_sum(outdir, counter, name_part):
     return total, disp
 
 
-def measure_traffic(args, opts, rtol):
-    """HBM bytes per call of the bulk-round kernel from two rocprofv3 counter
-    passes (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) over a probe run of
-    this script with the same options, each scaled by what the same counter
-    reads for a device copy of known size in the same run."""
+def measure_traffic(args, opts, rtol, mode=1):
+    """HBM bytes per call of the dominant integration kernel (mode 1: the
+    bulk rounds, 2: the sparse phase) from two rocprofv3 counter passes
+    (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) over a probe run of this
+    script with the same options, each scaled by what the same counter reads
+    for a device copy of known size in the same run."""
     prof = shutil.which("rocprofv3")
     if prof is None:
         return None, "rocprofv3 not found"
@@ -199,7 +200,7 @@ def measure_traffic(args, opts, rtol):
         if p.returncode != 0:
             shutil.rmtree(d, ignore_errors=True)
             return None, f"rocprofv3 --pmc {counter} exited with {p.returncode}: {p.stderr[-300:]}"
-        kern, nk = _pmc_sum(d, counter, "k_integrate<Mech_m9, 1>")
+        kern, nk = _pmc_sum(d, counter, f"k_integrate<Mech_m9, {mode}>")
         copy, nc = _pmc_sum(d, counter, "copyBuffer")
         if nk == 0:
             kern, nk = _pmc_sum(d, counter, "k_integrate_coop")
@@ -356,9 +357,9 @@ def main():
         kern, f_k, t_k = f"sparse-phase integration kernel ({sched})", f_rest, t_sparse
     achieved = f_k / (t_k * 1e-3) / 1e12
     traffic, traffic_detail = (None, "skipped (--no-traffic)")
-    if not args.no_traffic and kern.startswith("bulk"):
+    if not args.no_traffic:
         probe_opts = dict(tuned_opts, algorithm=1)
-        traffic, traffic_detail = measure_traffic(args, probe_opts, rtol)
+        traffic, traffic_detail = measure_traffic(args, probe_opts, rtol, 1 if kern.startswith("bulk") else 2)
     s_last = stats[-1]
     roofline = {
         "bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
