@@ -220,10 +220,10 @@ __global__ void __launch_bounds__(256) k_scatter_unfinished(const uint8_t* __res
 // the number of tolerance units the state moves per dt at the start,
 // s = dt max_i |f_i(y0)| / (rtol |y0_i| + atol) (one RHS per active cell),
 // ranks cells by the work the integrator will spend on them.  Cells are
-// taken longest first (bucket 0 = largest s, one bucket per factor 2 of s),
+// taken longest first (bucket 0 = largest s, one bucket per factor sqrt 2 of s),
 // so long cells do not start last and leave a tail of idle lanes.  Results
 // do not depend on the order: each cell is integrated by itself.
-constexpr int COST_BUCKETS = 64;
+constexpr int COST_BUCKETS = 128;
 
 template <class M>
 __global__ void __launch_bounds__(256) k_cost_key(const Params<M>* __restrict__ Pp,
@@ -251,7 +251,7 @@ __global__ void __launch_bounds__(256) k_cost_key(const Params<M>* __restrict__ 
         for (int k = 0; k < M::N; k++) s = fmax(s, fabs(f[k]) / (rtol * fabs(y[k]) + atol));
         s *= B.dt;
         // s that is not finite (a state the integrator will reject) goes first
-        const int lg = isfinite(s) ? (int)fmin(floor(log2(fmax(s, 1.0))), (double)(COST_BUCKETS - 1)) : COST_BUCKETS - 1;
+        const int lg = isfinite(s) ? (int)fmin(floor(2.0 * log2(fmax(s, 1.0))), (double)(COST_BUCKETS - 1)) : COST_BUCKETS - 1;
         const int b = COST_BUCKETS - 1 - lg;
         key[slot] = (uint8_t)b;
         atomicAdd(&hist[b], 1);
