@@ -7,7 +7,8 @@ dt = 5e-9 s, FP64, at fixed error: the loosest rtol (of 1e-4 ... 1e-8, atol
 1e-14) at which the path's result stays within 1e-4 relative on species above
 1e-10 and 1 K of the oracle (rtol 1e-12 / atol 1e-20) on a stratified sample
 of the field.  One step = one chem_integrate call over the whole patch
-(screen, bulk rounds, compaction, sparse phase) with the autotuned schedule;
+(screen, compaction, bulk rounds if the autotuner keeps any, sparse phase)
+with the autotuned schedule;
 every timed step starts from its own pristine copy of the initial state,
 resident in HBM before the timed region.  Prints one JSON line with the
 roofline of the dominant kernel, the comparison paths (plain all-cells FP64,
