@@ -883,7 +883,8 @@ __global__ void k_next_kmax(const unsigned* __restrict__ hist, const int* __rest
 
 // a wave refills once this many of its LW cell-carrying lanes are free (7/8:
 // on the detonation patch with LW = 63 every value from 48 to 60 was within
-// noise of the best, 3-4% faster than 24; on the AMR boxes 9%)
+// noise of the best, 3-4% faster than 24; on the AMR boxes 9%).  The sparse
+// phase waits for the whole wave: 1.5-2% faster again when it runs alone
 template <int LW> constexpr int refill_min() { return LW * 7 / 8; }
 
 template <class M, int MODE>
@@ -926,11 +927,12 @@ __global__ void __launch_bounds__(64) k_integrate(const Params<M>* __restrict__ 
             }
         } else {
             // lanes refill together: a wave takes new cells once refill_min of
-            // its lanes are free (or none is busy), so the starting steps of
+            // its lanes are free (or none is busy; in the sparse phase, whose
+            // cells come in cost order, only then), so the starting steps of
             // new cells, which every lane of the wave executes, run for many
             // cells at once instead of for one or two per attempt
             const bool refill = wave_ballot(cur >= 0) == 0 ||
-                                __popcll(wave_ballot(cur < 0 && !exhausted)) >= refill_min<LW>();
+                                __popcll(wave_ballot(cur < 0 && !exhausted)) >= (MODE == SPARSE ? LW : refill_min<LW>());
             for (; refill;) {
                 const bool need = cur < 0 && !exhausted;
                 const unsigned long long m = wave_ballot(need);
