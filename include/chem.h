@@ -173,7 +173,7 @@ void chem_ctx_destroy(chem_ctx_t c);
  *   order         0 (default) or 1: lanes take the cells longest first.  The
  *                 first round orders the active cells by a predicted cost, the
  *                 number of tolerance units the state moves per dt at the start,
- *                 dt max_i |f_i(y0)| / (rtol |y0_i| + atol), in factor-sqrt(2) buckets;
+ *                 dt max_i |f_i(y0)| / (rtol |y0_i| + atol), in factor-2^(1/4) buckets;
  *                 later rounds and the sparse phase take the cells the last
  *                 round saved by their predicted remaining attempts, the round's
  *                 pace extrapolated to t_end, att (dt - t) / (t - t_start), in

@@ -220,10 +220,10 @@ __global__ void __launch_bounds__(256) k_scatter_unfinished(const uint8_t* __res
 // the number of tolerance units the state moves per dt at the start,
 // s = dt max_i |f_i(y0)| / (rtol |y0_i| + atol) (one RHS per active cell),
 // ranks cells by the work the integrator will spend on them.  Cells are
-// taken longest first (bucket 0 = largest s, one bucket per factor sqrt 2 of s),
+// taken longest first (bucket 0 = largest s, one bucket per factor 2^(1/4) of s),
 // so long cells do not start last and leave a tail of idle lanes.  Results
 // do not depend on the order: each cell is integrated by itself.
-constexpr int COST_BUCKETS = 128;
+constexpr int COST_BUCKETS = 256;
 
 template <class M>
 __global__ void __launch_bounds__(256) k_cost_key(const Params<M>* __restrict__ Pp,
@@ -251,7 +251,7 @@ __global__ void __launch_bounds__(256) k_cost_key(const Params<M>* __restrict__ 
         for (int k = 0; k < M::N; k++) s = fmax(s, fabs(f[k]) / (rtol * fabs(y[k]) + atol));
         s *= B.dt;
         // s that is not finite (a state the integrator will reject) goes first
-        const int lg = isfinite(s) ? (int)fmin(floor(2.0 * log2(fmax(s, 1.0))), (double)(COST_BUCKETS - 1)) : COST_BUCKETS - 1;
+        const int lg = isfinite(s) ? (int)fmin(floor(4.0 * log2(fmax(s, 1.0))), (double)(COST_BUCKETS - 1)) : COST_BUCKETS - 1;
         const int b = COST_BUCKETS - 1 - lg;
         key[slot] = (uint8_t)b;
         atomicAdd(&hist[b], 1);
@@ -273,10 +273,21 @@ __global__ void __launch_bounds__(256) k_bucket_scatter(const uint8_t* __restric
     const int64_t slot = blockIdx.x * 256ll + threadIdx.x;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int b = slot < n ? (int)key[slot] : -1;
+    for (int i = threadIdx.x; i < 4 * COST_BUCKETS; i += 256) wc[i / COST_BUCKETS][i % COST_BUCKETS] = 0;
+    __syncthreads();
+    // one pass per bucket present in the wave (the first pending lane's):
+    // each lane's rank among the wave's lanes of its bucket, and the counts
     int within = 0;
-    for (int bb = 0; bb < COST_BUCKETS; bb++) {
-        const unsigned long long m = wave_ballot(b == bb);
-        if (b == bb) within = __popcll(m & ((1ull << lane) - 1ull));
+    bool pending = b >= 0;
+    for (;;) {
+        const unsigned long long pm = wave_ballot(pending);
+        if (!pm) break;
+        const int bb = __shfl(b, __ffsll((long long)pm) - 1);
+        const unsigned long long m = wave_ballot(pending && b == bb);
+        if (pending && b == bb) {
+            within = __popcll(m & ((1ull << lane) - 1ull));
+            pending = false;
+        }
         if (lane == 0) wc[w][bb] = __popcll(m);
     }
     __syncthreads();
